@@ -1,0 +1,155 @@
+"""Oracle of the OF-MLMC estimator (Sec. 2.4 of arXiv:1705.04374), NumPy FP64.
+
+TEST INFRASTRUCTURE ONLY (tests, smoke check, CPU baseline).
+
+Terms are indexed l = 0..L.  Term 0 holds M_0 single samples q_0^i; term l >= 1
+holds M_l coupled pairs (q_l^i, q_{l-1}^i) drawn with the same omega
+(eq. (mlmc), eq. (ocv-mlmc)).  W_l is the cost of one sample of term l: a
+single solve for l = 0, a pair of solves for l >= 1 (Sec. 2.4.1).
+
+Readings where the paper leaves a choice:
+  * variances and covariances are the unbiased 1/(M-1) two-pass estimates of
+    each term's own fine and coarse members; the coefficient system uses them
+    row by row (which is the exact minimiser of the estimated cost
+    C(alpha) = sum_l W_l Var(alpha_l q_l - alpha_{l-1} q_{l-1}),
+    eq. (cv-mlmc-var)); with a single variance per level it is the matrix of
+    eq. (alpha-matvec) verbatim;
+  * the tolerance is on eps (eps^2 <= tau^2), as in eq. (M-tol);
+  * samples with a failed status are left out of the moments (Sec. 2.5, FT-MLMC).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def term_moments(qf, qc=None, ok=None) -> dict:
+    """Two-pass moments of one term (step 3 of the adaptive algorithm)."""
+    qf = np.asarray(qf, dtype=np.float64)
+    if ok is not None:
+        keep = np.asarray(ok, dtype=bool)
+        qf = qf[keep]
+        if qc is not None:
+            qc = np.asarray(qc, dtype=np.float64)[keep]
+    M = qf.size
+    mf = float(np.sum(qf) / M) if M else 0.0
+    out = dict(M=M, mean_f=mf, mean_c=0.0, Vf=0.0, Vc=0.0, C=0.0)
+    if qc is not None:
+        qc = np.asarray(qc, dtype=np.float64)
+        out["mean_c"] = float(np.sum(qc) / M) if M else 0.0
+    if M >= 2:
+        df = qf - mf
+        out["Vf"] = float(np.sum(df * df) / (M - 1))
+        if qc is not None:
+            dc = qc - out["mean_c"]
+            out["Vc"] = float(np.sum(dc * dc) / (M - 1))
+            out["C"] = float(np.sum(df * dc) / (M - 1))
+    return out
+
+
+def coefficient_matrix(Vf, Vc, C, W):
+    """Tridiagonal system of eq. (alpha-matvec) for alpha_0..alpha_{L-1}
+    (alpha_L = 1).  Row k is d C(alpha) / d alpha_k = 0."""
+    L = len(W) - 1
+    A = np.zeros((L, L))
+    b = np.zeros(L)
+    for k in range(L):
+        A[k, k] = Vf[k] * W[k] + Vc[k + 1] * W[k + 1]
+        if k >= 1:
+            A[k, k - 1] = -C[k] * W[k]
+        if k + 1 <= L - 1:
+            A[k, k + 1] = -C[k + 1] * W[k + 1]
+    b[L - 1] = C[L] * W[L]
+    return A, b
+
+
+def coefficients(Vf, Vc, C, W) -> np.ndarray:
+    """Optimal control-variate coefficients alpha_0..alpha_L (alpha_L = 1),
+    step 4 of the adaptive algorithm."""
+    L = len(W) - 1
+    alpha = np.ones(L + 1)
+    if L == 0:
+        return alpha
+    A, b = coefficient_matrix(Vf, Vc, C, W)
+    alpha[:L] = np.linalg.solve(A, b)
+    return alpha
+
+
+def term_variances(Vf, Vc, C, alpha) -> np.ndarray:
+    """sigma~^2_l = Var(alpha_l q_l - alpha_{l-1} q_{l-1}) (eq. (ocv-mlmc-err))."""
+    L = len(alpha) - 1
+    s = np.zeros(L + 1)
+    s[0] = alpha[0] ** 2 * Vf[0]
+    for l in range(1, L + 1):
+        s[l] = alpha[l] ** 2 * Vf[l] + alpha[l - 1] ** 2 * Vc[l] - 2.0 * alpha[l] * alpha[l - 1] * C[l]
+    return s
+
+
+def error2(sig_t2, M) -> float:
+    """Estimated squared sampling error eps^2_OF = sum_l sigma~^2_l / M_l."""
+    return float(sum(s / m for s, m in zip(sig_t2, M)))
+
+
+def estimate(mean_f, mean_c, alpha) -> float:
+    """OF-MLMC estimator eq. (ocv-mlmc)."""
+    L = len(alpha) - 1
+    e = alpha[0] * mean_f[0]
+    for l in range(1, L + 1):
+        e += alpha[l] * mean_f[l] - alpha[l - 1] * mean_c[l]
+    return float(e)
+
+
+def warmup_samples(W, floor: int = 2):
+    """Warm-up sample counts eq. (warmup), then at least `floor` per term."""
+    L = len(W) - 1
+    return [max(floor, int(math.ceil(W[L] / W[l] / 2.0 ** (L - l)))) for l in range(L + 1)]
+
+
+class InfeasibleTolerance(ValueError):
+    pass
+
+
+def optimal_samples(sig_t2, W, M_have, mode: str, target: float):
+    """Sample counts by eq. (M-tol) (mode 'tol', target tau) or eq. (M-budget)
+    (mode 'budget', target B), keeping samples already computed: levels whose
+    optimum falls below what they hold are fixed at it, their error (or cost)
+    is taken off the target, and the rest is optimised again, until no level
+    falls below (step 7 of the adaptive algorithm)."""
+    L = len(W) - 1
+    free = set(range(L + 1))
+    Mhat = [int(m) for m in M_have]
+    while True:
+        fixed = [l for l in range(L + 1) if l not in free]
+        if mode == "tol":
+            t2 = target * target - sum(sig_t2[l] / M_have[l] for l in fixed)
+            if t2 <= 0.0:
+                raise InfeasibleTolerance("tolerance exhausted by kept levels")
+        else:
+            B = target - sum(M_have[l] * W[l] for l in fixed)
+        S = sum(math.sqrt(sig_t2[l] * W[l]) for l in free)
+        changed = False
+        for l in sorted(free):
+            if mode == "tol":
+                m = math.ceil(math.sqrt(sig_t2[l] / W[l]) * S / t2)
+            else:
+                m = math.ceil(B * math.sqrt(sig_t2[l] / W[l]) / S) if (B > 0 and S > 0) else 0
+            Mhat[l] = int(m)
+        for l in sorted(free):
+            if Mhat[l] < M_have[l]:
+                Mhat[l] = int(M_have[l])
+                free.discard(l)
+                changed = True
+        if not changed or not free:
+            break
+    for l in range(L + 1):
+        if l not in free:
+            Mhat[l] = int(M_have[l])
+    return Mhat
+
+
+def mc_samples(var_L: float, eps: float) -> int:
+    """Plain Monte Carlo sample count for error eps at the finest level,
+    eq. (speedup) with the square of the ratio (the error of a mean of M
+    samples is sigma / sqrt(M))."""
+    return int(math.ceil(var_L / (eps * eps)))
