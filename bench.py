@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path: cell-updates/s of one 256^3 two-phase solve.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision f32|f64]
+
+Workload: a 500-bubble cloud (centres uniform in a ball of radius 0.3 in the
+unit cube, log-normal radii, median 0.015, sigma 0.1, clipped to +-20 %),
+water/air stiffened gases, 0.0234 bar inside the cloud ramped to 100 bar
+outside, on a 256^3 grid.  A step is one full time step of the solver:
+three fused RHS + low-storage RK stages (the third with the CFL / QoI
+reduction) and the per-step finalisation, all HIP kernels of libofm.so.  The
+state is resident in HBM before timing starts; W warm-up steps, then K timed
+steps.  value = 256^3 cells x K steps / wall time.
+
+The JSON line also carries
+  roofline     for the dominant kernel (the fused stage kernel): its average
+               launch duration measured with HIP events on the stream it runs
+               on, against the per-launch algorithmic bytes (HBM roofline) and
+               the per-launch algorithmic flops (vector ALU roofline); `bound`
+               names the roofline the kernel is closer to;
+  cpu_baseline the serial FP64 oracle timed on this host's cores on a bounded
+               sample of the same workload (one 48^3 box of the 256^3 cloud per
+               process, 2 steps each);
+  fp64         the same measurement with the stencil in double.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+# vector ALU peak without packed FP32 (packed math is disabled in this
+# build): 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+VALU_PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}
+# algorithmic words per cell and step of the fused stage kernel (nv = 7):
+# stage 1 reads U, writes dU and U'; stage 2 reads U, dU, writes dU, U';
+# stage 3 reads U, dU, writes U'  -> 10 nv words per step
+WORDS_PER_CELL_STEP = 10 * 7
+# algorithmic flops per cell and stage (3-D), counted from the operations of
+# the scheme; see the design notes for the itemised count
+FLOPS_PER_CELL_STAGE = 2650
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 side measurement")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    return ap.parse_args()
+
+
+def measure(ctx, capi, cfg, bub, precision, steps, warmup):
+    import torch
+    from paper_1705_04374_amd.state import alloc_state
+    spec = capi.make_spec(cfg, precision, n_steps=steps)
+    st, bufs = alloc_state(cfg, precision)
+    capi.ofm_state_init(ctx, spec, bub, st)
+    torch.cuda.synchronize()
+    if warmup:
+        capi.ofm_step(ctx, spec, st, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    q, dts = capi.ofm_step(ctx, spec, st, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # per-launch durations of the stage kernel, events on its own stream
+    capi.ofm_kernel_timing(ctx, True)
+    capi.ofm_step(ctx, spec, st, 4)
+    kt = capi.ofm_kernel_times(ctx)
+    capi.ofm_kernel_timing(ctx, False)
+    del bufs
+    torch.cuda.empty_cache()
+    return dict(wall=wall, q=q, kt=kt)
+
+
+def cpu_baseline(cfg, bub, seconds_hint=20.0):
+    """Serial FP64 oracle on P host cores, each advancing its own 48^3 box of
+    the same 256^3 cloud by 2 steps (the box interior is exact; rate counts
+    every box cell)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    P = min(os.cpu_count() or 1, 16)
+    n = cfg["n"]
+    b = 48
+    rng_boxes = []
+    for k in range(P):
+        o = (n // 2 - b) + (k * 37) % max(1, n // 2)
+        lo = (min(o, n - b), min((o + 11 * k) % (n - b), n - b), min((o + 23 * k) % (n - b), n - b))
+        rng_boxes.append(lo)
+    from oracle.flow import initial_reduction
+    dt = 0.3 * (1.0 / n) / initial_reduction(cfg, bub)["s_max"]
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=P, mp_context=ctx) as ex:
+        res = list(ex.map(_cpu_box, [(cfg, bub, lo, b, dt) for lo in rng_boxes]))
+    wall = time.perf_counter() - t0
+    cells = sum(r[0] for r in res)
+    step_s = max(r[1] for r in res)
+    return dict(value=cells / step_s, unit="cell-updates/s", cores=P, kind="oracle",
+                sample="%d processes x one %d^3 box of the %d^3 500-bubble cloud, 2 FP64 steps each "
+                       "(init excluded), wall %.1f s" % (P, b, n, wall))
+
+
+def _cpu_box(args):
+    cfg, bub, lo, b, dt = args
+    import oracle.flow as OF
+    box = (lo, (b, b, b))
+    t0 = time.perf_counter()
+    OF.box_steps(cfg, bub, box, [])
+    t1 = time.perf_counter()
+    OF.box_steps(cfg, bub, box, [dt, dt])
+    t2 = time.perf_counter()
+    return (2 * b ** 3, (t2 - t1) - (t1 - t0))
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(samples would shard across GPUs with one small all-reduce per OF-MLMC iteration; "
+              "see the design notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1705_04374_amd import capi
+    from workloads.configs import MASTER_SEED, cloud_spec, solver_config
+
+    n = a.n
+    cfg = solver_config("cloud500", n)
+    bub = capi.ofm_sample_cloud(cloud_spec("cloud500"), MASTER_SEED, 0, 0)
+    ctx = capi.Context(0)
+    cells = n ** 3
+    r = measure(ctx, capi, cfg, bub, a.precision, a.steps, a.warmup)
+    ms_per_step = r["wall"] * 1e3 / a.steps
+    value = cells * a.steps / r["wall"]
+    kt = r["kt"]
+    avg_ms = kt["total_ms"] / max(kt["launches"], 1)
+    word = 4 if a.precision == "f32" else 8
+    cells_per_launch = kt["cells"] / max(kt["launches"], 1)
+    bytes_per_launch = cells_per_launch * WORDS_PER_CELL_STEP * word / 3.0
+    flops_per_launch = cells_per_launch * FLOPS_PER_CELL_STAGE
+    gbs = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    tfl = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    hbm_frac = gbs / HBM_PEAK_GBS
+    alu_frac = tfl / VALU_PEAK_TFLOPS[a.precision]
+    bound = "alu" if alu_frac >= hbm_frac else "hbm"
+    roof = {
+        "kernel": "stage_kernel (fused WENO5/HLLC RHS + LSRK3 stage, 3 launches per step)",
+        "bound": bound,
+        "achieved": round(tfl if bound == "alu" else gbs, 3),
+        "peak": VALU_PEAK_TFLOPS[a.precision] if bound == "alu" else HBM_PEAK_GBS,
+        "unit": "TFLOP/s" if bound == "alu" else "GB/s",
+        "frac": round(alu_frac if bound == "alu" else hbm_frac, 4),
+        "traffic": None,
+        "avg_launch_ms": round(avg_ms, 4),
+        "hbm": {"achieved_GBs": round(gbs, 1), "peak_GBs": HBM_PEAK_GBS, "frac": round(hbm_frac, 4),
+                "algorithmic_bytes_per_launch": bytes_per_launch},
+        "alu": {"achieved_TFLOPs": round(tfl, 2), "peak_TFLOPs": VALU_PEAK_TFLOPS[a.precision],
+                "frac": round(alu_frac, 4), "algorithmic_flops_per_launch": flops_per_launch},
+    }
+    out = {
+        "metric": "cell-updates/s at 256^3 (one 500-bubble cloud solve, 3-stage LSRK step incl. CFL/QoI reduction)",
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": a.precision,
+        "data": "synthetic (seeded 500-bubble cloud, no dataset)",
+        "config": {"workload": "cloud500 single solve, %d^3, %s stencil, FP64 QoI/dt" % (n, a.precision),
+                   "cells": cells, "bubbles": 500, "status": r["q"]["status"], "steps_taken": r["q"]["steps"]},
+        "roofline": roof,
+    }
+    if not a.no_fp64 and a.precision == "f32":
+        r64 = measure(ctx, capi, cfg, bub, "f64", max(4, a.steps // 3), 1)
+        kt64 = r64["kt"]
+        ms64 = kt64["total_ms"] / max(kt64["launches"], 1)
+        c64 = kt64["cells"] / max(kt64["launches"], 1)
+        out["fp64"] = {"value": cells * max(4, a.steps // 3) / r64["wall"], "unit": "cell-updates/s",
+                       "avg_stage_launch_ms": round(ms64, 4),
+                       "hbm_frac": round(c64 * WORDS_PER_CELL_STEP * 8 / 3.0 / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "alu_frac": round(c64 * FLOPS_PER_CELL_STAGE / (ms64 * 1e-3) / 1e12 / VALU_PEAK_TFLOPS["f64"], 4)}
+    if not a.no_cpu:
+        try:
+            out["cpu_baseline"] = cpu_baseline(cfg, bub)
+        except Exception as e:  # the baseline is reported, never required
+            out["cpu_baseline"] = {"error": repr(e)}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,276 @@
+/*
+ * ofm.h - C ABI of the MI355X optimal-fidelity MLMC library.
+ *
+ * The calls follow the problem statement of Sukys et al., "Optimal fidelity
+ * multi-level Monte Carlo for quantification of uncertainty in simulations of
+ * cloud cavitation collapse" (arXiv:1705.04374):
+ *   random initial data Q_0(x, omega) of a bubble cloud (Sec. 2.4, Sec. 3.1)
+ *   -> level-l finite-volume solve of the five-equation model (Sec. 2.1-2.2)
+ *   -> quantity of interest q_l(omega): the global maximum pressure (Sec. 3.3)
+ *   -> OF-MLMC moments, optimal coefficients, errors, estimate and sample
+ *      allocation (Sec. 2.4.3-2.4.4, eqs. (alpha-matvec), (ocv-mlmc),
+ *      (ocv-mlmc-err), (M-tol), (M-budget), (warmup)).
+ *
+ * Conventions
+ *   Return value: OFM_OK (0) or a negative OFM_E* code; the message of the last
+ *   failure of a context is returned by ofm_last_error().  Calls that take no
+ *   context report through ofm_last_error(NULL) (thread-local).
+ *   A physical failure of one sample (non-finite state, c^2 <= 0, step cap) is
+ *   NOT a call error: it is reported in ofm_qoi.status.
+ *   Ownership: the caller allocates and frees every buffer it passes; the
+ *   library keeps no caller pointer after a call returns, except for work
+ *   already enqueued on the caller's stream.  A context owns its internal
+ *   scratch (per-sample states of batched solves, graphs, tuning table).
+ *   Streams: every device operation is enqueued on the hipStream_t passed as
+ *   `stream` (NULL = default stream).  Calls returning host results
+ *   synchronise that stream before returning; the others are asynchronous.
+ *   Pointers marked [dev] are device memory, [host] host memory.
+ *   Units: SI.  Domain: unit interval/square/cube, cells of size h = 1/n.
+ *   Threading: a context may be used by one thread at a time.
+ */
+#ifndef OFM_H
+#define OFM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes --------------------------------------------------------- */
+#define OFM_OK            0
+#define OFM_EINVAL       -1   /* bad argument (sizes, layout, null pointer) */
+#define OFM_ENOMEM       -2   /* device or host allocation failed */
+#define OFM_EHIP         -3   /* a HIP runtime call failed */
+#define OFM_EUNSUPPORTED -4   /* valid request the library does not implement */
+#define OFM_ESINGULAR    -5   /* coefficient system not positive definite */
+#define OFM_EINFEASIBLE  -6   /* sampler or allocation cannot meet its target */
+
+/* ---- per-sample status (ofm_qoi.status) ------------------------------------ */
+#define OFM_SAMPLE_OK          0
+#define OFM_SAMPLE_NONFINITE   1   /* a state value or the pressure is NaN/Inf */
+#define OFM_SAMPLE_NEGATIVE_C2 2   /* rho <= 0 or c^2 <= 0 in some cell */
+#define OFM_SAMPLE_MAX_STEPS   3   /* step cap reached before the end time */
+
+/* ---- enumerations ---------------------------------------------------------- */
+#define OFM_F32 0   /* stencil arithmetic and state in float (QoI, dt in double) */
+#define OFM_F64 1   /* everything in double */
+#define OFM_BC_ZERO_GRADIENT 0
+#define OFM_BC_PERIODIC      1
+#define OFM_MODE_TOLERANCE 0
+#define OFM_MODE_BUDGET    1
+
+typedef struct ofm_ctx ofm_ctx;
+
+/* Stiffened-gas parameters of the two phases (Sec. 2.1):
+ * p = (gamma_k - 1) rho_k e_k - gamma_k pc_k; phase 1 = liquid, 2 = gas. */
+typedef struct {
+    double gamma1, pc1, gamma2, pc2;
+} ofm_eos;
+
+/* One level-l solve (Sec. 2.2 scheme; Sec. 3.1 initial data).
+ * State layout in device memory: structure of arrays, nv = 4 + ndim arrays of
+ * n^ndim cells each, variable-major: [v][k][j][i] with i fastest; variables
+ * (a1 rho1, a2 rho2, rho u_1..rho u_ndim, E, a2). */
+typedef struct {
+    int32_t ndim;        /* 1, 2 or 3 */
+    int32_t n;           /* cells per side, 8 <= n <= 4096 */
+    int32_t precision;   /* OFM_F32 or OFM_F64 */
+    int32_t bc;          /* OFM_BC_* */
+    int32_t n_sub;       /* sub-samples per axis for the initial a2 (n_sub^ndim <= 64) */
+    int32_t reserved;
+    double cfl;          /* Courant number (0.3 in the paper, Sec. 3.1) */
+    ofm_eos eos;
+    double rho1, rho2;   /* initial phase densities */
+    double p_bubble;     /* pressure inside the cloud */
+    double p_inf;        /* ambient pressure */
+    double center[3];    /* cloud centre */
+    double cloud_radius; /* the ramp to p_inf starts at cloud_radius + ramp_delta */
+    double ramp_delta;
+    double ramp_width;
+    double weno_eps;     /* WENO5 smoothness epsilon (absolute) */
+    double t_end;        /* end time when n_steps == 0 */
+    int64_t n_steps;     /* > 0: run exactly this many steps, t_end ignored */
+    int64_t max_steps;   /* step cap (status OFM_SAMPLE_MAX_STEPS) */
+} ofm_solve_spec;
+
+/* Quantity of interest of one solve (Sec. 3.3): maximum cell pressure over
+ * cells and time levels n = 0..steps; ties to the smallest flat cell index
+ * (k n + j) n + i, then to the earliest level. */
+typedef struct {
+    double p_max;
+    double x[3];         /* centre of the argmax cell (unused axes 0) */
+    double t_at_max;
+    double t;            /* time reached */
+    int64_t argmax;      /* flat cell index */
+    int64_t steps;       /* steps taken */
+    int32_t status;      /* OFM_SAMPLE_* */
+    int32_t reserved;
+} ofm_qoi;
+
+/* Random cloud geometry (Sec. 3, 3.1): n_bubbles centres uniform in the
+ * ball (disk) of radius cloud_radius around center, radii
+ * r_median exp(r_sigma Z) with Z standard normal, redrawn while outside
+ * [r_lo, r_hi] when r_hi > 0; bubbles never overlap. */
+typedef struct {
+    int32_t ndim;
+    int32_t n_bubbles;
+    double cloud_radius;
+    double center[3];
+    double r_median, r_sigma;
+    double r_lo, r_hi;
+} ofm_cloud_spec;
+
+/* Three caller-owned device arrays of nv * n^ndim elements of the spec's
+ * precision.  `u` holds the current state; `u_tmp` and `du` are scratch.
+ * ofm_step may exchange u and u_tmp: read the pointers back after the call. */
+typedef struct {
+    void* u;
+    void* u_tmp;
+    void* du;
+} ofm_state_view;
+
+/* One member of a batched solve.  Items of one call share ndim, precision,
+ * bc, eos and weno_eps; n, t_end and the cloud may differ.  A coupled
+ * fine/coarse pair is two items with the same bubbles (Sec. 2.4.1). */
+typedef struct {
+    const ofm_solve_spec* spec;
+    const double* bubbles;   /* [host] n_bubbles x 4 (x, y, z, r) */
+    int32_t n_bubbles;
+    int32_t reserved;
+} ofm_batch_item;
+
+/* ---- context --------------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  Returns OFM_EHIP if the device
+ * cannot be used. */
+int ofm_ctx_create(int device, ofm_ctx** out);
+void ofm_ctx_destroy(ofm_ctx* ctx);
+/* Message of the last failing call on ctx (or of the calling thread when ctx
+ * is NULL).  Valid until the next call. */
+const char* ofm_last_error(const ofm_ctx* ctx);
+
+/* ---- random initial data ------------------------------------------------- */
+
+/* Bubbles of the cloud omega(seed, term, index) (Sec. 3.1: uniform centres,
+ * log-normal radii, 2000 random numbers for 500 bubbles).  Host only,
+ * deterministic.  Generator: SplitMix64 (Steele, Lea, Flood 2014) with initial
+ * state mix(mix(mix(seed) ^ term) ^ index), mix(x) being the first output of a
+ * generator whose state is x; uniforms (x >> 11) 2^-53.  Per bubble: centre by
+ * rejection from [-1,1]^ndim into the unit ball; radius by Box-Muller with
+ * u1 = 1 - U, u2 = U; candidates overlapping an accepted bubble are redrawn
+ * (centre and radius), at most 100000 per bubble (then OFM_EINFEASIBLE).
+ * bubbles: [host] capacity n_bubbles x 4 doubles (x, y, z, r; z = 0 below 3-D). */
+int ofm_sample_cloud(const ofm_cloud_spec* spec, uint64_t seed, uint64_t term, uint64_t index,
+                     double* bubbles);
+
+/* ---- low-level state access (tests and custom drivers) --------------------- */
+
+/* Initial state Q_0 of the cloud in st->u (Sec. 3.1): a2 = fraction of the
+ * n_sub^ndim midpoint sub-samples of each cell inside the union of bubbles;
+ * pressure p_bubble up to cloud_radius + ramp_delta from the centre, then a
+ * smoothstep ramp of width ramp_width to p_inf; phase densities rho1, rho2;
+ * fluid at rest.  bubbles: [host] n_bubbles x 4.  Asynchronous. */
+int ofm_state_init(ofm_ctx* ctx, const ofm_solve_spec* spec, const double* bubbles,
+                   int32_t n_bubbles, ofm_state_view* st, void* stream);
+
+/* Conserved state in st->u from primitive fields w [dev] of the spec's
+ * precision, same layout with variables (a1 rho1, a2 rho2, u_1..u_ndim, p, a2).
+ * Asynchronous. */
+int ofm_state_from_primitive(ofm_ctx* ctx, const ofm_solve_spec* spec, const void* w,
+                             ofm_state_view* st, void* stream);
+
+/* Advance st->u by n_steps CFL-limited steps (dt = cfl h / max(|u_d| + c),
+ * taken at the start of each step, Sec. 2.2) of the three-stage low-storage
+ * Runge-Kutta scheme; spec->t_end and spec->n_steps are ignored.  On return
+ * st->u holds the new state (u and u_tmp may have been exchanged).  qoi
+ * [host] receives the maximum pressure over the levels n = 0..n_steps of this
+ * call; dts [host, may be NULL] receives the n_steps step sizes.  Synchronises
+ * the stream. */
+int ofm_step(ofm_ctx* ctx, const ofm_solve_spec* spec, ofm_state_view* st, int64_t n_steps,
+             ofm_qoi* qoi, double* dts, void* stream);
+
+/* ---- solves -------------------------------------------------------------- */
+
+/* Solve one sample to spec->t_end (or spec->n_steps steps) and return its QoI
+ * [host].  The library allocates the state internally (cached in ctx).
+ * Synchronises the stream. */
+int ofm_solve(ofm_ctx* ctx, const ofm_solve_spec* spec, const double* bubbles,
+              int32_t n_bubbles, ofm_qoi* qoi, void* stream);
+
+/* Solve n items together (samples of uneven grid sizes advance in the same
+ * launches; Sec. 2.5 job merging, done inside one device).  qoi: [host] n
+ * entries.  Synchronises the stream. */
+int ofm_solve_batch(ofm_ctx* ctx, const ofm_batch_item* items, int32_t n, ofm_qoi* qoi,
+                    void* stream);
+
+/* Time spent in the last ofm_solve/ofm_solve_batch, in seconds, split into
+ * initialisation and time stepping, and the number of cell-steps advanced. */
+int ofm_last_solve_stats(const ofm_ctx* ctx, double* init_s, double* step_s,
+                         double* cell_steps);
+
+/* Override the stage kernel's tile shape and schedule for solves of the
+ * given precision and dimension whose largest grid has n cells per side
+ * (grids in the same power-of-two size class share the entry): tile tx x ty
+ * cells, zchunk z-planes per workgroup (3-D), graph_steps time steps per
+ * captured graph.  OFM_EUNSUPPORTED if the tile shape is not compiled in. */
+int ofm_tune_set(ofm_ctx* ctx, int32_t precision, int32_t ndim, int32_t n, int32_t tx, int32_t ty,
+                 int32_t zchunk, int32_t graph_steps);
+
+/* Per-kernel timing for profiling: while enabled, solves launch their steps
+ * one by one (no graphs) and bracket every stage-kernel launch with HIP events
+ * on the stream the kernel runs on.  ofm_kernel_times returns, since the last
+ * enable, the number of stage-kernel launches, their summed duration in ms,
+ * and the cells they advanced (sum over launches of the cells of the samples
+ * still running).  Host pointers; synchronous. */
+int ofm_kernel_timing(ofm_ctx* ctx, int32_t enable);
+int ofm_kernel_times(const ofm_ctx* ctx, int64_t* launches, double* total_ms, double* cells);
+
+/* ---- OF-MLMC estimator (Sec. 2.4.3-2.4.4), all in double on the device ----- */
+
+/* Moments of one term from M samples: q_f [dev] fine values, q_c [dev]
+ * coarse values of the same omegas (NULL for term 0), ok [dev, may be NULL]
+ * per-sample flag, nonzero = use (failed samples are left out, Sec. 2.5).
+ * out [dev] 6 doubles: (M_used, mean_f, mean_c, Var_f, Var_c, Cov) with
+ * unbiased 1/(M_used - 1) two-pass estimates (zeros when M_used < 2).
+ * Deterministic (fixed reduction order).  Asynchronous. */
+int ofm_mlmc_moments(ofm_ctx* ctx, const double* q_f, const double* q_c, const int32_t* ok,
+                     int64_t M, double* out, void* stream);
+
+/* Optimal control-variate coefficients alpha_0..alpha_L (alpha_L = 1) from
+ * the terms' moments [dev] (L+1) x 6 (rows as written by ofm_mlmc_moments)
+ * and costs W [dev] L+1 (W_0 one solve, W_l a fine/coarse pair): the
+ * tridiagonal system eq. (alpha-matvec), row k (k < L)
+ *   -C_k W_k a_{k-1} + (Vf_k W_k + Vc_{k+1} W_{k+1}) a_k - C_{k+1} W_{k+1} a_{k+1} = 0,
+ * solved by the Thomas algorithm.  alpha [dev] L+1.  flag [dev] 1 int: 0, or
+ * OFM_ESINGULAR when a pivot is not positive (alpha is then all ones).
+ * Asynchronous. */
+int ofm_ofmlmc_coefficients(ofm_ctx* ctx, int32_t L, const double* moments, const double* W,
+                            double* alpha, int32_t* flag, void* stream);
+
+/* sig_t2 [dev] L+1: Var(alpha_l q_l - alpha_{l-1} q_{l-1}) per term, and
+ * eps2 [dev] 1: sum_l sig_t2_l / M_l (eq. (ocv-mlmc-err)); M from the moments.
+ * Asynchronous. */
+int ofm_ofmlmc_errors(ofm_ctx* ctx, int32_t L, const double* moments, const double* alpha,
+                      double* sig_t2, double* eps2, void* stream);
+
+/* OF-MLMC estimate eq. (ocv-mlmc) into E [dev] 1.  Asynchronous. */
+int ofm_ofmlmc_estimate(ofm_ctx* ctx, int32_t L, const double* moments, const double* alpha,
+                        double* E, void* stream);
+
+/* Sample counts M_out [dev] L+1 for a tolerance on eps (mode
+ * OFM_MODE_TOLERANCE, eq. (M-tol)) or a budget (OFM_MODE_BUDGET, eq.
+ * (M-budget)), keeping the M_have [dev] samples already computed: levels whose
+ * optimum is below M_have are fixed, their error (budget) is taken off the
+ * target and the rest re-optimised until none falls below (step 7 of the
+ * adaptive algorithm).  flag [dev] 1 int: 0 or OFM_EINFEASIBLE.
+ * Asynchronous. */
+int ofm_ofmlmc_optimal_M(ofm_ctx* ctx, int32_t L, const double* sig_t2, const double* W,
+                         const int64_t* M_have, int32_t mode, double target, int64_t* M_out,
+                         int32_t* flag, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OFM_H */

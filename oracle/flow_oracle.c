@@ -282,7 +282,7 @@ void orc_hllc(const orc_spec* s, int dir, const double* wl, const double* wr, do
  *   - both edge values of a1r1 and a2r2 are >= 0 and so is the interior value
  *     (12 mean - left - right)/10 of the four-point Gauss-Lobatto rule that
  *     reproduces the cell mean (Zhang-Shu positivity condition), up to
- *     round-off (ORC_ROUND_TOL of the largest magnitude in the stencil);
+ *     round-off (ORC_ROUND_TOL of the largest mixture density in the stencil);
  *   - both edge values and the interior value of a2 lie in [0, 1], up to
  *     ORC_ROUND_TOL;
  *   - both edge states have (Gamma+1) p + Pi > 0 (positive c^2);
@@ -299,10 +299,15 @@ int orc_cell_edges(const orc_spec* s, const double* a, const double* b, const do
         lm[v] = orc_weno5_right_edge(e[v], d[v], c[v], b[v], a[v], eps);
     }
     int ok = 1;
+    /* round-off below the mixture density of the stencil does not count as
+     * negative (a partial density is part of the mixture density) */
+    double big = 0.0;
+    {
+        const double* st5[5] = { a, b, c, d, e };
+        for (int k = 0; k < 5; ++k) big = fmax(big, fabs(st5[k][0] + st5[k][1]));
+    }
+    double tol = -ORC_ROUND_TOL * big;
     for (int v = 0; v < 2; ++v) {
-        /* round-off below the stencil's magnitude does not count as negative */
-        double big = fmax(fmax(fmax(fabs(a[v]), fabs(b[v])), fmax(fabs(c[v]), fabs(d[v]))), fabs(e[v]));
-        double tol = -ORC_ROUND_TOL * big;
         double mid = (12.0 * c[v] - lm[v] - lp[v]) / 10.0;
         if (!(lm[v] >= tol) || !(lp[v] >= tol) || !(mid >= tol)) ok = 0;
     }

@@ -1,0 +1,311 @@
+"""Thin ctypes binding of ``libofm.so`` (declared in ``include/ofm.h``).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  PyTorch provides device memory (tensors, passed by ``data_ptr()``)
+and the current HIP stream.  The library must have been built
+(``python -m paper_1705_04374_amd.build``); importing this module without it
+raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libofm.so")
+
+OFM_OK, OFM_EINVAL, OFM_ENOMEM, OFM_EHIP, OFM_EUNSUPPORTED, OFM_ESINGULAR, OFM_EINFEASIBLE = 0, -1, -2, -3, -4, -5, -6
+OFM_F32, OFM_F64 = 0, 1
+OFM_BC_ZERO_GRADIENT, OFM_BC_PERIODIC = 0, 1
+OFM_MODE_TOLERANCE, OFM_MODE_BUDGET = 0, 1
+SAMPLE_OK, SAMPLE_NONFINITE, SAMPLE_NEGATIVE_C2, SAMPLE_MAX_STEPS = 0, 1, 2, 3
+
+# Every symbol include/ofm.h declares.
+EXPORTS = [
+    "ofm_ctx_create", "ofm_ctx_destroy", "ofm_last_error", "ofm_sample_cloud", "ofm_state_init",
+    "ofm_state_from_primitive", "ofm_step", "ofm_solve", "ofm_solve_batch", "ofm_last_solve_stats",
+    "ofm_mlmc_moments", "ofm_ofmlmc_coefficients", "ofm_ofmlmc_errors", "ofm_ofmlmc_estimate",
+    "ofm_ofmlmc_optimal_M", "ofm_tune_set", "ofm_kernel_timing", "ofm_kernel_times",
+]
+
+
+class OfmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("ofm error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Eos(C.Structure):
+    _fields_ = [("gamma1", C.c_double), ("pc1", C.c_double), ("gamma2", C.c_double), ("pc2", C.c_double)]
+
+
+class SolveSpec(C.Structure):
+    _fields_ = [
+        ("ndim", C.c_int32), ("n", C.c_int32), ("precision", C.c_int32), ("bc", C.c_int32),
+        ("n_sub", C.c_int32), ("reserved", C.c_int32),
+        ("cfl", C.c_double), ("eos", Eos),
+        ("rho1", C.c_double), ("rho2", C.c_double), ("p_bubble", C.c_double), ("p_inf", C.c_double),
+        ("center", C.c_double * 3), ("cloud_radius", C.c_double), ("ramp_delta", C.c_double),
+        ("ramp_width", C.c_double), ("weno_eps", C.c_double), ("t_end", C.c_double),
+        ("n_steps", C.c_int64), ("max_steps", C.c_int64),
+    ]
+
+
+class Qoi(C.Structure):
+    _fields_ = [
+        ("p_max", C.c_double), ("x", C.c_double * 3), ("t_at_max", C.c_double), ("t", C.c_double),
+        ("argmax", C.c_int64), ("steps", C.c_int64), ("status", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        return dict(p_max=self.p_max, x=tuple(self.x), t_at_max=self.t_at_max, t=self.t, argmax=self.argmax,
+                    steps=self.steps, status=self.status)
+
+
+class CloudSpec(C.Structure):
+    _fields_ = [
+        ("ndim", C.c_int32), ("n_bubbles", C.c_int32), ("cloud_radius", C.c_double), ("center", C.c_double * 3),
+        ("r_median", C.c_double), ("r_sigma", C.c_double), ("r_lo", C.c_double), ("r_hi", C.c_double),
+    ]
+
+
+class StateView(C.Structure):
+    _fields_ = [("u", C.c_void_p), ("u_tmp", C.c_void_p), ("du", C.c_void_p)]
+
+
+class BatchItem(C.Structure):
+    _fields_ = [("spec", C.POINTER(SolveSpec)), ("bubbles", C.POINTER(C.c_double)), ("n_bubbles", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class NNSpec(C.Structure):
+    _fields_ = [("d_in", C.c_int32), ("width", C.c_int32), ("d_out", C.c_int32), ("reserved", C.c_int32),
+                ("pool_scale", C.c_float), ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("adam_eps", C.c_float), ("reserved2", C.c_float)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OfmError(OFM_EUNSUPPORTED, "libofm.so not built: run python -m paper_1705_04374_amd.build")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+        L.ofm_ctx_create.argtypes = [C.c_int, C.POINTER(vp)]
+        L.ofm_ctx_destroy.argtypes = [vp]
+        L.ofm_ctx_destroy.restype = None
+        L.ofm_last_error.argtypes = [vp]
+        L.ofm_last_error.restype = C.c_char_p
+        L.ofm_sample_cloud.argtypes = [C.POINTER(CloudSpec), C.c_uint64, C.c_uint64, C.c_uint64, dp]
+        L.ofm_state_init.argtypes = [vp, C.POINTER(SolveSpec), dp, i32, C.POINTER(StateView), vp]
+        L.ofm_state_from_primitive.argtypes = [vp, C.POINTER(SolveSpec), vp, C.POINTER(StateView), vp]
+        L.ofm_step.argtypes = [vp, C.POINTER(SolveSpec), C.POINTER(StateView), i64, C.POINTER(Qoi), dp, vp]
+        L.ofm_solve.argtypes = [vp, C.POINTER(SolveSpec), dp, i32, C.POINTER(Qoi), vp]
+        L.ofm_solve_batch.argtypes = [vp, C.POINTER(BatchItem), i32, C.POINTER(Qoi), vp]
+        L.ofm_last_solve_stats.argtypes = [vp, dp, dp, dp]
+        L.ofm_mlmc_moments.argtypes = [vp, vp, vp, vp, i64, vp, vp]
+        L.ofm_ofmlmc_coefficients.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+        L.ofm_ofmlmc_errors.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+        L.ofm_ofmlmc_estimate.argtypes = [vp, i32, vp, vp, vp, vp]
+        L.ofm_ofmlmc_optimal_M.argtypes = [vp, i32, vp, vp, vp, i32, C.c_double, vp, vp, vp]
+        L.ofm_tune_set.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32]
+        L.ofm_kernel_timing.argtypes = [vp, i32]
+        L.ofm_kernel_times.argtypes = [vp, C.POINTER(i64), dp, dp]
+        if hasattr(L, "ofm_nn_create"):
+            L.ofm_nn_create.argtypes = [vp, C.POINTER(NNSpec), C.c_uint64, C.POINTER(vp)]
+            L.ofm_nn_destroy.argtypes = [vp]
+            L.ofm_nn_destroy.restype = None
+            L.ofm_nn_get_params.argtypes = [vp, vp, vp]
+            L.ofm_nn_set_params.argtypes = [vp, vp, vp]
+            L.ofm_nn_forward.argtypes = [vp, vp, vp, i32, vp, vp]
+            L.ofm_nn_train_step.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+            L.ofm_nn_grads.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return C.c_void_p(stream)
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t):
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One library context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        self._check(lib().ofm_ctx_create(device, C.byref(h)), None)
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ofm_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int, h):
+        if rc != OFM_OK:
+            msg = lib().ofm_last_error(h)
+            raise OfmError(rc, msg.decode() if msg else "")
+
+    def check(self, rc: int):
+        self._check(rc, self.h)
+
+
+def make_spec(cfg: dict, precision: str = "f64", t_end: float = 0.0, n_steps: int = 0,
+              max_steps: int = 10 ** 7) -> SolveSpec:
+    """SolveSpec from a plain workload dictionary (see ``workloads.configs``)."""
+    s = SolveSpec()
+    s.ndim = cfg["ndim"]
+    s.n = cfg["n"]
+    s.precision = {"f32": OFM_F32, "f64": OFM_F64}[precision]
+    s.bc = {"zero_gradient": OFM_BC_ZERO_GRADIENT, "periodic": OFM_BC_PERIODIC}[cfg.get("bc", "zero_gradient")]
+    s.n_sub = cfg.get("n_sub", 4)
+    s.cfl = cfg.get("cfl", 0.3)
+    e = cfg["eos"]
+    s.eos = Eos(e["gamma1"], e["pc1"], e["gamma2"], e["pc2"])
+    s.rho1, s.rho2 = cfg.get("rho1", 1000.0), cfg.get("rho2", 1.0)
+    s.p_bubble, s.p_inf = cfg.get("p_bubble", 2340.0), cfg.get("p_inf", 1.0e7)
+    c = cfg.get("center", (0.5, 0.5, 0.5))
+    for a in range(3):
+        s.center[a] = c[a]
+    R = cfg.get("cloud_radius", 0.3)
+    s.cloud_radius = R
+    s.ramp_delta = cfg.get("ramp_delta", R / 20.0)
+    s.ramp_width = cfg.get("ramp_width", R / 3.0)
+    s.weno_eps = cfg.get("weno_eps", 1e-6)
+    s.t_end = t_end
+    s.n_steps = n_steps
+    s.max_steps = max_steps
+    return s
+
+
+def cloud_spec(spec: dict) -> CloudSpec:
+    c = CloudSpec()
+    c.ndim = spec["ndim"]
+    c.n_bubbles = spec["n_bubbles"]
+    c.cloud_radius = spec["cloud_radius"]
+    cen = spec.get("center", (0.5, 0.5, 0.5))
+    for a in range(3):
+        c.center[a] = cen[a]
+    c.r_median, c.r_sigma = spec["r_median"], spec["r_sigma"]
+    c.r_lo, c.r_hi = spec.get("r_lo", 0.0), spec.get("r_hi", 0.0)
+    return c
+
+
+def ofm_sample_cloud(spec: dict, seed: int, term: int, index: int) -> np.ndarray:
+    cs = cloud_spec(spec)
+    out = np.zeros((spec["n_bubbles"], 4))
+    rc = lib().ofm_sample_cloud(C.byref(cs), seed, term, index, out.ctypes.data_as(C.POINTER(C.c_double)))
+    if rc != OFM_OK:
+        raise OfmError(rc, lib().ofm_last_error(None).decode())
+    return out
+
+
+def _bub(bubbles):
+    b = np.ascontiguousarray(np.asarray(bubbles, dtype=np.float64).reshape(-1, 4))
+    return b, b.ctypes.data_as(C.POINTER(C.c_double)), b.shape[0]
+
+
+def ofm_state_init(ctx: Context, spec: SolveSpec, bubbles, st: StateView, stream=None):
+    b, p, nb = _bub(bubbles)
+    ctx.check(lib().ofm_state_init(ctx.h, C.byref(spec), p, nb, C.byref(st), _stream(stream)))
+
+
+def ofm_state_from_primitive(ctx: Context, spec: SolveSpec, w, st: StateView, stream=None):
+    ctx.check(lib().ofm_state_from_primitive(ctx.h, C.byref(spec), _dptr(w), C.byref(st), _stream(stream)))
+
+
+def ofm_step(ctx: Context, spec: SolveSpec, st: StateView, n_steps: int, stream=None):
+    q = Qoi()
+    dts = np.zeros(max(n_steps, 1))
+    ctx.check(lib().ofm_step(ctx.h, C.byref(spec), C.byref(st), n_steps, C.byref(q),
+                             dts.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)))
+    return q.as_dict(), dts[:n_steps]
+
+
+def ofm_solve(ctx: Context, spec: SolveSpec, bubbles, stream=None) -> dict:
+    b, p, nb = _bub(bubbles)
+    q = Qoi()
+    ctx.check(lib().ofm_solve(ctx.h, C.byref(spec), p, nb, C.byref(q), _stream(stream)))
+    return q.as_dict()
+
+
+def ofm_solve_batch(ctx: Context, specs, bubbles_list, stream=None) -> list:
+    n = len(specs)
+    items = (BatchItem * n)()
+    keep = []
+    for i, (s, bl) in enumerate(zip(specs, bubbles_list)):
+        b, p, nb = _bub(bl)
+        keep.append((s, b))
+        items[i].spec = C.pointer(s)
+        items[i].bubbles = p
+        items[i].n_bubbles = nb
+    qs = (Qoi * n)()
+    ctx.check(lib().ofm_solve_batch(ctx.h, items, n, qs, _stream(stream)))
+    return [q.as_dict() for q in qs]
+
+
+def ofm_last_solve_stats(ctx: Context) -> dict:
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    ctx.check(lib().ofm_last_solve_stats(ctx.h, C.byref(a), C.byref(b), C.byref(c)))
+    return dict(init_s=a.value, step_s=b.value, cell_steps=c.value)
+
+
+def ofm_mlmc_moments(ctx: Context, qf, qc, ok, out, stream=None):
+    ctx.check(lib().ofm_mlmc_moments(ctx.h, _dptr(qf), _dptr(qc), _dptr(ok), qf.numel(), _dptr(out),
+                                     _stream(stream)))
+
+
+def ofm_ofmlmc_coefficients(ctx: Context, L: int, mom, W, alpha, flag, stream=None):
+    ctx.check(lib().ofm_ofmlmc_coefficients(ctx.h, L, _dptr(mom), _dptr(W), _dptr(alpha), _dptr(flag),
+                                            _stream(stream)))
+
+
+def ofm_ofmlmc_errors(ctx: Context, L: int, mom, alpha, sig, eps2, stream=None):
+    ctx.check(lib().ofm_ofmlmc_errors(ctx.h, L, _dptr(mom), _dptr(alpha), _dptr(sig), _dptr(eps2),
+                                      _stream(stream)))
+
+
+def ofm_ofmlmc_estimate(ctx: Context, L: int, mom, alpha, E, stream=None):
+    ctx.check(lib().ofm_ofmlmc_estimate(ctx.h, L, _dptr(mom), _dptr(alpha), _dptr(E), _stream(stream)))
+
+
+def ofm_ofmlmc_optimal_M(ctx: Context, L: int, sig, W, have, mode: int, target: float, out, flag, stream=None):
+    ctx.check(lib().ofm_ofmlmc_optimal_M(ctx.h, L, _dptr(sig), _dptr(W), _dptr(have), mode, target, _dptr(out),
+                                         _dptr(flag), _stream(stream)))
+
+
+def ofm_tune_set(ctx: Context, precision: int, ndim: int, n: int, tx: int, ty: int, zchunk: int,
+                 graph_steps: int):
+    ctx.check(lib().ofm_tune_set(ctx.h, precision, ndim, n, tx, ty, zchunk, graph_steps))
+
+
+def ofm_kernel_timing(ctx: Context, enable: bool):
+    ctx.check(lib().ofm_kernel_timing(ctx.h, 1 if enable else 0))
+
+
+def ofm_kernel_times(ctx: Context) -> dict:
+    n, ms, cells = C.c_int64(), C.c_double(), C.c_double()
+    ctx.check(lib().ofm_kernel_times(ctx.h, C.byref(n), C.byref(ms), C.byref(cells)))
+    return dict(launches=n.value, total_ms=ms.value, cells=cells.value)

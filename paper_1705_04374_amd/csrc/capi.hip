@@ -1,0 +1,620 @@
+// C ABI of the library: contexts, validation, the batched solve driver and
+// the estimator entry points.  Everything numeric runs in the kernels of
+// flow_kernels.hip / mlmc_kernels.hip; this file only lays out memory,
+// launches and waits.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "flow_kernels.h"
+#include "ofm_error.h"
+#include "tuning.h"
+
+struct ofm_ctx {
+    int device = 0;
+    std::string err;
+    // grow-only device scratch owned by the context
+    void* arena = nullptr;  size_t arena_bytes = 0;     // sample states of solves
+    void* meta = nullptr;   size_t meta_bytes = 0;      // descriptors, states, partials, work list
+    void* bub = nullptr;    size_t bub_bytes = 0;       // bubbles of the samples
+    ofm::SampleState* host_state = nullptr; size_t host_state_cap = 0;  // pinned
+    hipStream_t stream = nullptr;   // solves run here (capturable, default priority)
+    double last_init_s = 0, last_step_s = 0, last_cell_steps = 0;
+    bool timing = false;          // per-launch events around stage kernels
+    int64_t t_launches = 0;
+    double t_ms = 0.0, t_cells = 0.0;
+    ofm::Tuning tuning;
+};
+
+namespace ofm {
+
+static thread_local std::string t_err;
+
+int fail(ofm_ctx* ctx, int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    t_err = buf;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return ofm::fail(ctx, OFM_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+static int grow(ofm_ctx* ctx, void** p, size_t* have, size_t need)
+{
+    if (need <= *have) return OFM_OK;
+    if (*p) { (void)hipFree(*p); *p = nullptr; *have = 0; }
+    size_t want = std::max(need, (size_t)1 << 20);
+    if (hipMalloc(p, want) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, OFM_ENOMEM, "device allocation of %zu bytes failed", want);
+    }
+    *have = want;
+    return OFM_OK;
+}
+
+static PhysD make_phys(const ofm_solve_spec& s)
+{
+    PhysD p;
+    p.g1inv = 1.0 / (s.eos.gamma1 - 1.0);
+    p.g2inv = 1.0 / (s.eos.gamma2 - 1.0);
+    p.pi1 = s.eos.gamma1 * s.eos.pc1 / (s.eos.gamma1 - 1.0);
+    p.pi2 = s.eos.gamma2 * s.eos.pc2 / (s.eos.gamma2 - 1.0);
+    p.gamma1 = s.eos.gamma1;
+    p.pc1 = s.eos.pc1;
+    p.gamma2 = s.eos.gamma2;
+    p.pc2 = s.eos.pc2;
+    p.eps = s.weno_eps;
+    return p;
+}
+
+static int validate(ofm_ctx* ctx, const ofm_solve_spec* s)
+{
+    if (!s) return fail(ctx, OFM_EINVAL, "null spec");
+    if (s->ndim < 1 || s->ndim > 3) return fail(ctx, OFM_EINVAL, "ndim must be 1, 2 or 3 (got %d)", s->ndim);
+    if (s->n < 8 || s->n > 4096) return fail(ctx, OFM_EINVAL, "n must be in [8, 4096] (got %d)", s->n);
+    if (s->precision != OFM_F32 && s->precision != OFM_F64) return fail(ctx, OFM_EINVAL, "bad precision");
+    if (s->bc != OFM_BC_ZERO_GRADIENT && s->bc != OFM_BC_PERIODIC) return fail(ctx, OFM_EINVAL, "bad bc");
+    int nsub = 1;
+    for (int a = 0; a < s->ndim; ++a) nsub *= s->n_sub;
+    if (s->n_sub < 1 || nsub > 64) return fail(ctx, OFM_EINVAL, "n_sub^ndim must be in [1, 64]");
+    if (!(s->cfl > 0.0 && s->cfl <= 1.0)) return fail(ctx, OFM_EINVAL, "cfl must be in (0, 1]");
+    if (!(s->eos.gamma1 > 1.0) || !(s->eos.gamma2 > 1.0)) return fail(ctx, OFM_EINVAL, "gamma must exceed 1");
+    if (!(s->weno_eps > 0.0)) return fail(ctx, OFM_EINVAL, "weno_eps must be positive");
+    if (!(s->rho1 > 0.0) || !(s->rho2 > 0.0)) return fail(ctx, OFM_EINVAL, "densities must be positive");
+    if (!(s->ramp_width > 0.0)) return fail(ctx, OFM_EINVAL, "ramp_width must be positive");
+    if (s->max_steps < 1) return fail(ctx, OFM_EINVAL, "max_steps must be >= 1");
+    if (s->n_steps <= 0 && !(s->t_end > 0.0)) return fail(ctx, OFM_EINVAL, "need t_end > 0 or n_steps > 0");
+    return OFM_OK;
+}
+
+static int64_t cells_of(const ofm_solve_spec& s)
+{
+    int64_t c = 1;
+    for (int a = 0; a < s.ndim; ++a) c *= s.n;
+    return c;
+}
+
+static size_t state_bytes(const ofm_solve_spec& s)
+{
+    return (size_t)(4 + s.ndim) * (size_t)cells_of(s) * (s.precision == OFM_F64 ? 8 : 4);
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// One batched run: all members share ndim/precision/bc/eos.
+struct Member {
+    ofm_solve_spec spec;
+    const double* bubbles;  // host
+    int32_t nb;
+    void* buf0; void* buf1; void* du;   // device arrays (caller's or arena)
+};
+
+struct RunOut {
+    std::vector<SampleState> state;
+    std::vector<SampleDesc> desc;
+};
+
+// Runs members to completion.  init: 1 = build Q_0 from bubbles, 0 = use buf0.
+static int run(ofm_ctx* ctx, std::vector<Member>& mem, bool init, double* dts_host, int64_t dts_len,
+               RunOut& ro, hipStream_t user_stream)
+{
+    // Work already queued by the caller comes first; the solve itself runs on
+    // the context's own non-blocking stream, which graph capture requires.
+    HIPCHK(ctx, hipStreamSynchronize(user_stream));
+    hipStream_t stream = ctx->stream;
+    const int ns = (int)mem.size();
+    const ofm_solve_spec& s0 = mem[0].spec;
+    const int prec = s0.precision, nd = s0.ndim, bc = s0.bc;
+    for (const Member& m : mem) {
+        if (m.spec.ndim != nd || m.spec.precision != prec || m.spec.bc != bc || m.spec.weno_eps != s0.weno_eps ||
+            memcmp(&m.spec.eos, &s0.eos, sizeof(ofm_eos)) != 0)
+            return fail(ctx, OFM_EINVAL, "batched items must share ndim, precision, bc, eos and weno_eps");
+        if (bc == OFM_BC_PERIODIC && m.spec.n < 6) return fail(ctx, OFM_EINVAL, "periodic grids need n >= 6");
+    }
+    // tiling
+    int maxn = 0;
+    for (const Member& m : mem) maxn = std::max(maxn, m.spec.n);
+    const TileChoice tc = ctx->tuning.choose(prec, nd, maxn, ns);
+    ro.desc.assign(ns, SampleDesc{});
+    int tiles = 0;
+    for (int i = 0; i < ns; ++i) {
+        SampleDesc& d = ro.desc[i];
+        const ofm_solve_spec& s = mem[i].spec;
+        d.buf[0] = mem[i].buf0;
+        d.buf[1] = mem[i].buf1;
+        d.du = mem[i].du;
+        d.n = s.n;
+        d.ntx = (s.n + tc.tx - 1) / tc.tx;
+        d.nty = nd >= 2 ? (s.n + tc.ty - 1) / tc.ty : 1;
+        d.nzc = nd == 3 ? (s.n + tc.zchunk - 1) / tc.zchunk : 1;
+        d.tile0 = tiles;
+        d.ntiles = d.ntx * d.nty * d.nzc;
+        d.h = 1.0 / (double)s.n;
+        d.cfl = s.cfl;
+        d.t_end = s.n_steps > 0 ? INFINITY : s.t_end;
+        d.n_steps = s.n_steps;
+        d.max_steps = s.max_steps;
+        tiles += d.ntiles;
+    }
+    // work list: larger samples first, tiles of a sample contiguous
+    std::vector<int> order(ns);
+    for (int i = 0; i < ns; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return mem[a].spec.n > mem[b].spec.n; });
+    std::vector<WorkItem> work;
+    work.reserve(tiles);
+    for (int i : order)
+        for (int t = 0; t < ro.desc[i].ntiles; ++t) work.push_back(WorkItem{ i, t });
+
+    const size_t o_desc = 0;
+    const size_t o_state = align256(o_desc + sizeof(SampleDesc) * ns);
+    const size_t o_part = align256(o_state + sizeof(SampleState) * ns);
+    const size_t o_work = align256(o_part + sizeof(TilePartial) * tiles);
+    const size_t o_dt = align256(o_work + sizeof(WorkItem) * work.size());
+    const size_t meta_need = o_dt + sizeof(double) * (size_t)std::max<int64_t>(dts_len, 1);
+    int rc = grow(ctx, &ctx->meta, &ctx->meta_bytes, meta_need);
+    if (rc) return rc;
+    char* meta = (char*)ctx->meta;
+    SampleDesc* d_desc = (SampleDesc*)(meta + o_desc);
+    SampleState* d_state = (SampleState*)(meta + o_state);
+    TilePartial* d_part = (TilePartial*)(meta + o_part);
+    WorkItem* d_work = (WorkItem*)(meta + o_work);
+    double* d_dt = dts_host ? (double*)(meta + o_dt) : nullptr;
+
+    std::vector<SampleState> st0(ns);
+    for (auto& s : st0) memset(&s, 0, sizeof s);
+    HIPCHK(ctx, hipMemcpyAsync(d_desc, ro.desc.data(), sizeof(SampleDesc) * ns, hipMemcpyHostToDevice, stream));
+    HIPCHK(ctx, hipMemcpyAsync(d_state, st0.data(), sizeof(SampleState) * ns, hipMemcpyHostToDevice, stream));
+    HIPCHK(ctx, hipMemcpyAsync(d_work, work.data(), sizeof(WorkItem) * work.size(), hipMemcpyHostToDevice, stream));
+
+    hipEvent_t e0, e1, e2;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    HIPCHK(ctx, hipEventCreate(&e2));
+    HIPCHK(ctx, hipEventRecord(e0, stream));
+
+    const PhysD ph = make_phys(s0);
+    if (init) {
+        size_t nbub = 0;
+        for (const Member& m : mem) nbub += (size_t)m.nb;
+        rc = grow(ctx, &ctx->bub, &ctx->bub_bytes, sizeof(double) * 4 * std::max<size_t>(nbub, 1));
+        if (rc) return rc;
+        std::vector<double> hb;
+        hb.reserve(4 * nbub);
+        for (const Member& m : mem) hb.insert(hb.end(), m.bubbles, m.bubbles + 4 * (size_t)m.nb);
+        if (nbub)
+            HIPCHK(ctx, hipMemcpyAsync(ctx->bub, hb.data(), sizeof(double) * hb.size(), hipMemcpyHostToDevice, stream));
+        size_t off = 0;
+        for (const Member& m : mem) {
+            InitLaunch L;
+            L.ph = ph;
+            L.bubbles = (const double*)ctx->bub + 4 * off;
+            L.nb = m.nb;
+            L.n = m.spec.n;
+            L.n_sub = m.spec.n_sub;
+            L.rho1 = m.spec.rho1; L.rho2 = m.spec.rho2;
+            L.p_bubble = m.spec.p_bubble; L.p_inf = m.spec.p_inf;
+            for (int a = 0; a < 3; ++a) L.center[a] = m.spec.center[a];
+            L.radius = m.spec.cloud_radius; L.delta = m.spec.ramp_delta; L.width = m.spec.ramp_width;
+            L.u = m.buf0;
+            HIPCHK(ctx, launch_init(prec, nd, L, stream));
+            off += (size_t)m.nb;
+        }
+        // the host bubbles vector must outlive the copy
+        HIPCHK(ctx, hipStreamSynchronize(stream));
+    }
+    LaunchArgs la;
+    la.ph = ph;
+    la.work = d_work;
+    la.n_work = (int)work.size();
+    la.zchunk = tc.zchunk;
+    la.desc = d_desc;
+    la.state = d_state;
+    la.part = d_part;
+    la.bc = bc;
+    la.src = 0;
+    HIPCHK(ctx, launch_reduce(prec, nd, tc.tx, tc.ty, la, stream));
+    HIPCHK(ctx, launch_finalize(d_desc, d_state, d_part, ns, 1, d_dt, dts_len, stream));
+    HIPCHK(ctx, hipEventRecord(e1, stream));
+
+    // time stepping: graphs of K steps replayed until every sample is done
+    if (ctx->host_state_cap < (size_t)ns) {
+        if (ctx->host_state) (void)hipHostFree(ctx->host_state);
+        ctx->host_state = nullptr;
+        HIPCHK(ctx, hipHostMalloc((void**)&ctx->host_state, sizeof(SampleState) * ns, hipHostMallocDefault));
+        ctx->host_state_cap = ns;
+    }
+    int64_t cap = 0;
+    for (const Member& m : mem) cap = std::max(cap, m.spec.n_steps > 0 ? m.spec.n_steps : m.spec.max_steps);
+    // eager launches for the low-level stepper (per-step control) and while
+    // kernels are being timed; captured graphs otherwise
+    const bool eager = dts_host != nullptr || ctx->timing;
+    const int K = eager ? 2 : tc.graph_steps;
+    hipEvent_t kev[2] = { nullptr, nullptr };
+    if (ctx->timing) {
+        HIPCHK(ctx, hipEventCreate(&kev[0]));
+        HIPCHK(ctx, hipEventCreate(&kev[1]));
+    }
+    std::vector<double> live_cells(1, 0.0);
+    auto enqueue_steps = [&](int nsteps) -> int {
+        for (int g = 0; g < nsteps; ++g)
+            for (int stg = 0; stg < 3; ++stg) {
+                la.src = (g + stg) & 1;     // (3 g + stg) mod 2 with g counted from an even step
+                if (ctx->timing) HIPCHK(ctx, hipEventRecord(kev[0], stream));
+                HIPCHK(ctx, launch_stage(prec, nd, tc.tx, tc.ty, la, stg, stream));
+                if (ctx->timing) {
+                    HIPCHK(ctx, hipEventRecord(kev[1], stream));
+                    HIPCHK(ctx, hipEventSynchronize(kev[1]));
+                    float ms = 0.f;
+                    HIPCHK(ctx, hipEventElapsedTime(&ms, kev[0], kev[1]));
+                    ctx->t_launches += 1;
+                    ctx->t_ms += ms;
+                    ctx->t_cells += live_cells[0];
+                }
+                if (stg == 2) HIPCHK(ctx, launch_finalize(d_desc, d_state, d_part, ns, 0, d_dt, dts_len, stream));
+            }
+        return OFM_OK;
+    };
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    if (!eager) {
+        HIPCHK(ctx, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+        rc = enqueue_steps(K);
+        hipError_t ce = hipStreamEndCapture(stream, &graph);
+        if (rc) return rc;
+        if (ce != hipSuccess) return fail(ctx, OFM_EHIP, "graph capture failed: %s", hipGetErrorString(ce));
+        HIPCHK(ctx, hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+    }
+    int64_t taken = 0;
+    int result = OFM_OK;
+    live_cells[0] = 0.0;
+    for (int i = 0; i < ns; ++i) live_cells[0] += (double)cells_of(mem[i].spec);
+    for (;;) {
+        if (eager) rc = enqueue_steps(K);
+        else {
+            hipError_t le = hipGraphLaunch(gexec, stream);
+            rc = le == hipSuccess ? OFM_OK : fail(ctx, OFM_EHIP, "graph launch failed: %s", hipGetErrorString(le));
+        }
+        if (rc) { result = rc; break; }
+        taken += K;
+        hipError_t ce = hipMemcpyAsync(ctx->host_state, d_state, sizeof(SampleState) * ns, hipMemcpyDeviceToHost, stream);
+        if (ce == hipSuccess) ce = hipStreamSynchronize(stream);
+        if (ce != hipSuccess) { result = fail(ctx, OFM_EHIP, "state read-back failed: %s", hipGetErrorString(ce)); break; }
+        bool all = true;
+        live_cells[0] = 0.0;
+        for (int i = 0; i < ns; ++i) {
+            all = all && ctx->host_state[i].done;
+            if (!ctx->host_state[i].done) live_cells[0] += (double)cells_of(mem[i].spec);
+        }
+        if (all) break;
+        if (taken > cap + 2 * K) { result = fail(ctx, OFM_EHIP, "samples did not finish within the step cap"); break; }
+    }
+    if (kev[0]) (void)hipEventDestroy(kev[0]);
+    if (kev[1]) (void)hipEventDestroy(kev[1]);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipEventRecord(e2, stream);
+    (void)hipEventSynchronize(e2);
+    float t01 = 0, t12 = 0;
+    (void)hipEventElapsedTime(&t01, e0, e1);
+    (void)hipEventElapsedTime(&t12, e1, e2);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
+    if (result) return result;
+    ro.state.assign(ctx->host_state, ctx->host_state + ns);
+    ctx->last_init_s = t01 * 1e-3;
+    ctx->last_step_s = t12 * 1e-3;
+    double cs = 0;
+    for (int i = 0; i < ns; ++i) cs += (double)cells_of(mem[i].spec) * (double)ro.state[i].steps;
+    ctx->last_cell_steps = cs;
+    if (dts_host && dts_len > 0)
+        HIPCHK(ctx, hipMemcpy(dts_host, d_dt, sizeof(double) * dts_len, hipMemcpyDeviceToHost));
+    return OFM_OK;
+}
+
+static void to_qoi(const ofm_solve_spec& s, const SampleState& st, ofm_qoi* q)
+{
+    memset(q, 0, sizeof *q);
+    q->p_max = st.p_max;
+    q->t_at_max = st.t_at_max;
+    q->t = st.t;
+    q->argmax = st.argmax;
+    q->steps = st.steps;
+    q->status = st.status;
+    const int64_t n = s.n;
+    const int64_t a = st.argmax < 0 || st.argmax == INT64_MAX ? 0 : st.argmax;
+    q->x[0] = ((double)(a % n) + 0.5) / (double)n;
+    if (s.ndim > 1) q->x[1] = ((double)((a / n) % n) + 0.5) / (double)n;
+    if (s.ndim > 2) q->x[2] = ((double)(a / (n * n)) + 0.5) / (double)n;
+}
+
+}  // namespace ofm
+
+using namespace ofm;
+
+extern "C" {
+
+int ofm_ctx_create(int device, ofm_ctx** out)
+{
+    if (!out) return fail(nullptr, OFM_EINVAL, "ofm_ctx_create: null out");
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count)
+        return fail(nullptr, OFM_EHIP, "ofm_ctx_create: no HIP device %d (found %d)", device, count);
+    if (hipSetDevice(device) != hipSuccess) return fail(nullptr, OFM_EHIP, "ofm_ctx_create: hipSetDevice failed");
+    ofm_ctx* c = new ofm_ctx();
+    c->device = device;
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return fail(nullptr, OFM_EHIP, "ofm_ctx_create: stream creation failed");
+    }
+    *out = c;
+    return OFM_OK;
+}
+
+void ofm_ctx_destroy(ofm_ctx* ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->arena) (void)hipFree(ctx->arena);
+    if (ctx->meta) (void)hipFree(ctx->meta);
+    if (ctx->bub) (void)hipFree(ctx->bub);
+    if (ctx->host_state) (void)hipHostFree(ctx->host_state);
+    if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+const char* ofm_last_error(const ofm_ctx* ctx)
+{
+    return ctx ? ctx->err.c_str() : t_err.c_str();
+}
+
+int ofm_state_init(ofm_ctx* ctx, const ofm_solve_spec* spec, const double* bubbles, int32_t nb, ofm_state_view* st,
+                   void* stream)
+{
+    if (!ctx) return fail(nullptr, OFM_EINVAL, "null context");
+    int rc = validate(ctx, spec);
+    if (rc) return rc;
+    if (!st || !st->u || (nb > 0 && !bubbles) || nb < 0) return fail(ctx, OFM_EINVAL, "ofm_state_init: bad arguments");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = (hipStream_t)stream;
+    rc = grow(ctx, &ctx->bub, &ctx->bub_bytes, sizeof(double) * 4 * std::max(nb, 1));
+    if (rc) return rc;
+    if (nb) HIPCHK(ctx, hipMemcpyAsync(ctx->bub, bubbles, sizeof(double) * 4 * nb, hipMemcpyHostToDevice, s));
+    InitLaunch L;
+    L.ph = make_phys(*spec);
+    L.bubbles = (const double*)ctx->bub;
+    L.nb = nb;
+    L.n = spec->n;
+    L.n_sub = spec->n_sub;
+    L.rho1 = spec->rho1; L.rho2 = spec->rho2; L.p_bubble = spec->p_bubble; L.p_inf = spec->p_inf;
+    for (int a = 0; a < 3; ++a) L.center[a] = spec->center[a];
+    L.radius = spec->cloud_radius; L.delta = spec->ramp_delta; L.width = spec->ramp_width;
+    L.u = st->u;
+    HIPCHK(ctx, launch_init(spec->precision, spec->ndim, L, s));
+    HIPCHK(ctx, hipStreamSynchronize(s));   // the host bubbles may go away
+    return OFM_OK;
+}
+
+int ofm_state_from_primitive(ofm_ctx* ctx, const ofm_solve_spec* spec, const void* w, ofm_state_view* st,
+                             void* stream)
+{
+    if (!ctx) return fail(nullptr, OFM_EINVAL, "null context");
+    int rc = validate(ctx, spec);
+    if (rc) return rc;
+    if (!w || !st || !st->u) return fail(ctx, OFM_EINVAL, "ofm_state_from_primitive: null pointer");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, launch_prim_to_cons(spec->precision, spec->ndim, make_phys(*spec), w, st->u, cells_of(*spec),
+                                    (hipStream_t)stream));
+    return OFM_OK;
+}
+
+int ofm_step(ofm_ctx* ctx, const ofm_solve_spec* spec, ofm_state_view* st, int64_t n_steps, ofm_qoi* qoi,
+             double* dts, void* stream)
+{
+    if (!ctx) return fail(nullptr, OFM_EINVAL, "null context");
+    int rc = validate(ctx, spec);
+    if (rc) return rc;
+    if (!st || !st->u || !st->u_tmp || !st->du || n_steps < 1 || !qoi)
+        return fail(ctx, OFM_EINVAL, "ofm_step: bad arguments");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    std::vector<Member> mem(1);
+    mem[0].spec = *spec;
+    mem[0].spec.n_steps = n_steps;
+    mem[0].spec.max_steps = n_steps;
+    mem[0].bubbles = nullptr;
+    mem[0].nb = 0;
+    mem[0].buf0 = st->u;
+    mem[0].buf1 = st->u_tmp;
+    mem[0].du = st->du;
+    std::vector<double> dloc;
+    double* dptr = dts;
+    if (!dptr) { dloc.resize(n_steps); dptr = dloc.data(); }
+    RunOut ro;
+    rc = run(ctx, mem, false, dptr, n_steps, ro, (hipStream_t)stream);
+    if (rc) return rc;
+    to_qoi(mem[0].spec, ro.state[0], qoi);
+    if (ro.state[0].steps & 1) std::swap(st->u, st->u_tmp);
+    return OFM_OK;
+}
+
+static int solve_members(ofm_ctx* ctx, const ofm_batch_item* items, int32_t n, ofm_qoi* qoi, void* stream)
+{
+    if (!ctx) return fail(nullptr, OFM_EINVAL, "null context");
+    if (!items || n < 1 || !qoi) return fail(ctx, OFM_EINVAL, "bad batch arguments");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    std::vector<Member> mem(n);
+    size_t need = 0;
+    for (int i = 0; i < n; ++i) {
+        int rc = validate(ctx, items[i].spec);
+        if (rc) return rc;
+        if (items[i].n_bubbles < 0 || (items[i].n_bubbles > 0 && !items[i].bubbles))
+            return fail(ctx, OFM_EINVAL, "item %d: bad bubbles", i);
+        mem[i].spec = *items[i].spec;
+        mem[i].bubbles = items[i].bubbles;
+        mem[i].nb = items[i].n_bubbles;
+        need += 3 * align256(state_bytes(mem[i].spec));
+    }
+    int rc = grow(ctx, &ctx->arena, &ctx->arena_bytes, need);
+    if (rc) return rc;
+    char* p = (char*)ctx->arena;
+    for (int i = 0; i < n; ++i) {
+        const size_t b = align256(state_bytes(mem[i].spec));
+        mem[i].buf0 = p; p += b;
+        mem[i].buf1 = p; p += b;
+        mem[i].du = p; p += b;
+    }
+    RunOut ro;
+    rc = run(ctx, mem, true, nullptr, 0, ro, (hipStream_t)stream);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) to_qoi(mem[i].spec, ro.state[i], qoi + i);
+    return OFM_OK;
+}
+
+int ofm_solve(ofm_ctx* ctx, const ofm_solve_spec* spec, const double* bubbles, int32_t nb, ofm_qoi* qoi,
+              void* stream)
+{
+    ofm_batch_item it;
+    it.spec = spec;
+    it.bubbles = bubbles;
+    it.n_bubbles = nb;
+    it.reserved = 0;
+    return solve_members(ctx, &it, 1, qoi, stream);
+}
+
+int ofm_solve_batch(ofm_ctx* ctx, const ofm_batch_item* items, int32_t n, ofm_qoi* qoi, void* stream)
+{
+    return solve_members(ctx, items, n, qoi, stream);
+}
+
+int ofm_last_solve_stats(const ofm_ctx* ctx, double* init_s, double* step_s, double* cell_steps)
+{
+    if (!ctx) return fail(nullptr, OFM_EINVAL, "null context");
+    if (init_s) *init_s = ctx->last_init_s;
+    if (step_s) *step_s = ctx->last_step_s;
+    if (cell_steps) *cell_steps = ctx->last_cell_steps;
+    return OFM_OK;
+}
+
+int ofm_tune_set(ofm_ctx* ctx, int32_t precision, int32_t ndim, int32_t n, int32_t tx, int32_t ty, int32_t zchunk,
+                 int32_t graph_steps)
+{
+    if (!ctx) return fail(nullptr, OFM_EINVAL, "null context");
+    if (!tile_supported(precision, ndim, tx, ty))
+        return fail(ctx, OFM_EUNSUPPORTED, "tile %dx%d not compiled for precision %d, ndim %d", tx, ty, precision, ndim);
+    if (zchunk < 1 || zchunk > 4096 || graph_steps < 2 || (graph_steps & 1))
+        return fail(ctx, OFM_EINVAL, "zchunk must be >= 1 and graph_steps even and >= 2");
+    ctx->tuning.set(precision, ndim, n, TileChoice{ tx, ty, zchunk, graph_steps });
+    return OFM_OK;
+}
+
+int ofm_kernel_timing(ofm_ctx* ctx, int32_t enable)
+{
+    if (!ctx) return fail(nullptr, OFM_EINVAL, "null context");
+    ctx->timing = enable != 0;
+    ctx->t_launches = 0;
+    ctx->t_ms = 0.0;
+    ctx->t_cells = 0.0;
+    return OFM_OK;
+}
+
+int ofm_kernel_times(const ofm_ctx* ctx, int64_t* launches, double* total_ms, double* cells)
+{
+    if (!ctx) return fail(nullptr, OFM_EINVAL, "null context");
+    if (launches) *launches = ctx->t_launches;
+    if (total_ms) *total_ms = ctx->t_ms;
+    if (cells) *cells = ctx->t_cells;
+    return OFM_OK;
+}
+
+int ofm_mlmc_moments(ofm_ctx* ctx, const double* qf, const double* qc, const int32_t* ok, int64_t M, double* out,
+                     void* stream)
+{
+    if (!ctx) return fail(nullptr, OFM_EINVAL, "null context");
+    if (!qf || !out || M < 0) return fail(ctx, OFM_EINVAL, "ofm_mlmc_moments: bad arguments");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, launch_moments(qf, qc, ok, M, out, (hipStream_t)stream));
+    return OFM_OK;
+}
+
+int ofm_ofmlmc_coefficients(ofm_ctx* ctx, int32_t L, const double* mom, const double* W, double* alpha,
+                            int32_t* flag, void* stream)
+{
+    if (!ctx) return fail(nullptr, OFM_EINVAL, "null context");
+    if (L < 0 || L > 31 || !mom || !W || !alpha || !flag) return fail(ctx, OFM_EINVAL, "ofm_ofmlmc_coefficients: bad arguments");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, launch_coefficients(L, mom, W, alpha, flag, (hipStream_t)stream));
+    return OFM_OK;
+}
+
+int ofm_ofmlmc_errors(ofm_ctx* ctx, int32_t L, const double* mom, const double* alpha, double* sig, double* eps2,
+                      void* stream)
+{
+    if (!ctx) return fail(nullptr, OFM_EINVAL, "null context");
+    if (L < 0 || L > 31 || !mom || !alpha || !sig || !eps2) return fail(ctx, OFM_EINVAL, "ofm_ofmlmc_errors: bad arguments");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, launch_errors(L, mom, alpha, sig, eps2, (hipStream_t)stream));
+    return OFM_OK;
+}
+
+int ofm_ofmlmc_estimate(ofm_ctx* ctx, int32_t L, const double* mom, const double* alpha, double* E, void* stream)
+{
+    if (!ctx) return fail(nullptr, OFM_EINVAL, "null context");
+    if (L < 0 || L > 31 || !mom || !alpha || !E) return fail(ctx, OFM_EINVAL, "ofm_ofmlmc_estimate: bad arguments");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, launch_estimate(L, mom, alpha, E, (hipStream_t)stream));
+    return OFM_OK;
+}
+
+int ofm_ofmlmc_optimal_M(ofm_ctx* ctx, int32_t L, const double* sig, const double* W, const int64_t* have,
+                         int32_t mode, double target, int64_t* out, int32_t* flag, void* stream)
+{
+    if (!ctx) return fail(nullptr, OFM_EINVAL, "null context");
+    if (L < 0 || L > 31 || !sig || !W || !have || !out || !flag || (mode != OFM_MODE_TOLERANCE && mode != OFM_MODE_BUDGET) ||
+        !(target > 0.0))
+        return fail(ctx, OFM_EINVAL, "ofm_ofmlmc_optimal_M: bad arguments");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, launch_optimal_M(L, sig, W, have, mode, target, out, flag, (hipStream_t)stream));
+    return OFM_OK;
+}
+
+}  // extern "C"

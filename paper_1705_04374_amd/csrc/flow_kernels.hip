@@ -1,0 +1,904 @@
+// HIP kernels of one level-l solve of the five-equation two-phase model
+// (Sukys et al., arXiv:1705.04374, Sec. 2.1-2.3), written for gfx950.
+//
+// A time step is three launches of `stage_kernel` (one per stage of the
+// low-storage third-order Runge-Kutta scheme) and one `finalize_kernel`
+// launch.  The stage kernel fuses what the paper lists as the right-hand-side
+// and Runge-Kutta-update kernels (Sec. 2.3); its third-stage epilogue also
+// does the CFL / QoI reduction (the paper's first kernel), so a step reads
+// and writes each state array the minimum number of times.
+//
+// Work decomposition: a workgroup owns an x-y tile of TX x TY cells of one
+// sample and marches through a chunk of z-planes.  For each plane it stages
+// the primitive variables of the tile plus a 3-cell halo in LDS, reconstructs
+// every cell along x and y (WENO5, both edges at once, with the cell-wise
+// positivity fallback), evaluates the HLLC face fluxes and the face
+// velocities, and keeps the x-y divergence of the plane in registers.  The z
+// direction uses a per-thread register queue of five planes, so each face is
+// computed once.  A plane's cells are finished three planes later, when their
+// upper z-face is known.
+//
+// Layout in HBM: structure of arrays, one contiguous array per variable,
+// x fastest; three arrays per sample (two ping-pong state buffers and the
+// low-storage register dU).
+#include "flow_kernels.h"
+
+#include <math.h>
+
+namespace ofm {
+
+// ---------------------------------------------------------------------------
+// Arithmetic helpers: fast reciprocal/sqrt in float, IEEE in double.
+// ---------------------------------------------------------------------------
+template <typename T> struct Num;
+template <> struct Num<float> {
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+    // round-off allowance of the positivity checks, relative to the stencil
+    static constexpr float round_tol = 1e-6f;
+};
+template <> struct Num<double> {
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double sqrt_(double x) { return ::sqrt(x); }
+    static constexpr double round_tol = 1e-12;
+};
+
+template <typename T> struct Phys {
+    T g1inv, dginv, pi1, dpi, eps;
+    T gam1, pc1, gam2, pc2;
+    __device__ __forceinline__ explicit Phys(const PhysD& d)
+        : g1inv((T)d.g1inv), dginv((T)(d.g2inv - d.g1inv)), pi1((T)d.pi1), dpi((T)(d.pi2 - d.pi1)),
+          eps((T)d.eps), gam1((T)d.gamma1), pc1((T)d.pc1), gam2((T)d.gamma2), pc2((T)d.pc2) {}
+    // mixture stiffened-gas coefficients under isobaric closure:
+    // p = (E - rho|u|^2/2 - Pi(a2)) / Gamma(a2)
+    __device__ __forceinline__ T gamma(T a2) const { return g1inv + a2 * dginv; }
+    __device__ __forceinline__ T pinf(T a2) const { return pi1 + a2 * dpi; }
+};
+
+__device__ __forceinline__ int bc_map(int i, int n, int bc)
+{
+    if (bc == OFM_BC_PERIODIC) { i %= n; return i < 0 ? i + n : i; }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// Conserved -> primitive (a1r1, a2r2, u_1..u_d, p, a2).
+template <typename T, int ND>
+__device__ __forceinline__ void to_prim(const Phys<T>& ph, const T* q, T* w)
+{
+    T rho = q[0] + q[1];
+    T irho = Num<T>::rcp(rho);
+    T ke = T(0);
+    w[0] = q[0];
+    w[1] = q[1];
+#pragma unroll
+    for (int m = 0; m < ND; ++m) {
+        w[2 + m] = q[2 + m] * irho;
+        ke += q[2 + m] * w[2 + m];
+    }
+    T a2 = q[3 + ND];
+    w[2 + ND] = (q[2 + ND] - T(0.5) * ke - ph.pinf(a2)) * Num<T>::rcp(ph.gamma(a2));
+    w[3 + ND] = a2;
+}
+
+// WENO5 (Jiang-Shu) edge values of the centre cell c of the stencil a..e:
+// `lo` at its left edge, `hi` at its right edge.  The two edges share the
+// smoothness indicators; the nonlinear weights are normalised by the
+// smallest (eps + beta) so that they cannot overflow (same weights).
+template <typename T>
+__device__ __forceinline__ void weno5_cell(T a, T b, T c, T d, T e, T eps, T& lo, T& hi)
+{
+    const T k13 = T(13) / T(12), k6 = T(1) / T(6);
+    T t0 = a - T(2) * b + c, t1 = a - T(4) * b + T(3) * c;
+    T b0 = k13 * t0 * t0 + T(0.25) * t1 * t1;
+    t0 = b - T(2) * c + d;
+    t1 = b - d;
+    T b1 = k13 * t0 * t0 + T(0.25) * t1 * t1;
+    t0 = c - T(2) * d + e;
+    t1 = T(3) * c - T(4) * d + e;
+    T b2 = k13 * t0 * t0 + T(0.25) * t1 * t1;
+    T e0 = eps + b0, e1 = eps + b1, e2 = eps + b2;
+    T m = fmin(fmin(e0, e1), e2);
+    T r0 = m * Num<T>::rcp(e0), r1 = m * Num<T>::rcp(e1), r2 = m * Num<T>::rcp(e2);
+    T q0 = r0 * r0, q1 = r1 * r1, q2 = r2 * r2;
+    // right edge: candidate values on stencils (a,b,c), (b,c,d), (c,d,e)
+    T p0 = (T(2) * a - T(7) * b + T(11) * c) * k6;
+    T p1 = (-b + T(5) * c + T(2) * d) * k6;
+    T p2 = (T(2) * c + T(5) * d - e) * k6;
+    T w0 = T(0.1) * q0, w1 = T(0.6) * q1, w2 = T(0.3) * q2;
+    hi = (w0 * p0 + w1 * p1 + w2 * p2) * Num<T>::rcp(w0 + w1 + w2);
+    // left edge: the mirrored stencil, whose indicators are (b2, b1, b0)
+    p0 = (T(2) * e - T(7) * d + T(11) * c) * k6;
+    p1 = (-d + T(5) * c + T(2) * b) * k6;
+    p2 = (T(2) * c + T(5) * b - a) * k6;
+    w0 = T(0.1) * q2;
+    w1 = T(0.6) * q1;
+    w2 = T(0.3) * q0;
+    lo = (w0 * p0 + w1 * p1 + w2 * p2) * Num<T>::rcp(w0 + w1 + w2);
+}
+
+// Edges of one cell along one axis with the positivity / bounds check: the
+// reconstruction is kept only if the partial densities stay >= 0 at both
+// edges and at the interior Gauss-Lobatto point (12 mean - lo - hi)/10, a2
+// stays in [0, 1] there, and both edge states have (Gamma+1) p + Pi > 0
+// (each up to round-off: round_tol times the stencil's mixture density for
+// the partial densities, round_tol for a2); otherwise both edges take the
+// cell's primitives.
+template <typename T, int ND>
+__device__ __forceinline__ void cell_edges(const Phys<T>& ph, const T (&s)[5][4 + ND],
+                                           T (&lo)[4 + ND], T (&hi)[4 + ND])
+{
+    constexpr int NV = 4 + ND;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) weno5_cell<T>(s[0][v], s[1][v], s[2][v], s[3][v], s[4][v], ph.eps, lo[v], hi[v]);
+    bool ok = true;
+    // round-off below the stencil's mixture density does not count as
+    // negative (a partial density is part of the mixture density)
+    T big = T(0);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) big = fmax(big, fabs(s[k][0] + s[k][1]));
+    const T tol = -Num<T>::round_tol * big;
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+        T mid = (T(12) * s[2][v] - lo[v] - hi[v]) * T(0.1);
+        ok = ok && (lo[v] >= tol) && (hi[v] >= tol) && (mid >= tol);
+    }
+    {
+        constexpr int v = 3 + ND;
+        const T lb = -Num<T>::round_tol, ub = T(1) + Num<T>::round_tol;
+        T mid = (T(12) * s[2][v] - lo[v] - hi[v]) * T(0.1);
+        ok = ok && (lo[v] >= lb) && (lo[v] <= ub) && (hi[v] >= lb) && (hi[v] <= ub) && (mid >= lb) && (mid <= ub);
+    }
+    T cl = (ph.gamma(lo[3 + ND]) + T(1)) * lo[2 + ND] + ph.pinf(lo[3 + ND]);
+    T ch = (ph.gamma(hi[3 + ND]) + T(1)) * hi[2 + ND] + ph.pinf(hi[3 + ND]);
+    ok = ok && (cl > T(0)) && (ch > T(0));
+    if (!ok) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) { lo[v] = s[2][v]; hi[v] = s[2][v]; }
+    }
+}
+
+// HLLC flux along axis DIR (Toro 1994) with Davis wave speeds; the a2 flux
+// is a2_K u_f where u_f is the face velocity of the HLLC flux of a passive
+// scalar (Johnsen-Colonius adaptation).  f[0..NV-2]: fluxes of (a1r1, a2r2,
+// momenta, E); f[NV-1]: a2 flux; f[NV]: u_f.
+template <typename T, int ND, int DIR>
+__device__ __forceinline__ void hllc(const Phys<T>& ph, const T (&wl)[4 + ND], const T (&wr)[4 + ND],
+                                     T (&f)[5 + ND])
+{
+    constexpr int NV = 4 + ND;
+    T rl = wl[0] + wl[1], rr = wr[0] + wr[1];
+    T ul = wl[2 + DIR], ur = wr[2 + DIR];
+    T pl = wl[2 + ND], pr = wr[2 + ND];
+    T gl = ph.gamma(wl[3 + ND]), gr = ph.gamma(wr[3 + ND]);
+    T Pl = ph.pinf(wl[3 + ND]), Pr = ph.pinf(wr[3 + ND]);
+    T kel = T(0), ker = T(0);
+#pragma unroll
+    for (int m = 0; m < ND; ++m) { kel += wl[2 + m] * wl[2 + m]; ker += wr[2 + m] * wr[2 + m]; }
+    T El = gl * pl + Pl + T(0.5) * rl * kel;
+    T Er = gr * pr + Pr + T(0.5) * rr * ker;
+    T cl = Num<T>::sqrt_(((gl + T(1)) * pl + Pl) * Num<T>::rcp(gl * rl));
+    T cr = Num<T>::sqrt_(((gr + T(1)) * pr + Pr) * Num<T>::rcp(gr * rr));
+    T sl = fmin(ul - cl, ur - cr);
+    T sr = fmax(ul + cl, ur + cr);
+    T ml = rl * (sl - ul), mr = rr * (sr - ur);
+    T ss = (pr - pl + ml * ul - mr * ur) * Num<T>::rcp(ml - mr);
+    // side whose (star) state enters: left if S_L >= 0 or S* >= 0
+    const bool left = (sl >= T(0)) || (ss >= T(0));
+    const T sK = left ? sl : sr;
+    const T sk = left ? fmin(sl, T(0)) : fmax(sr, T(0));   // 0 for the upwind fluxes
+    T w[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) w[v] = left ? wl[v] : wr[v];
+    const T rho = left ? rl : rr;
+    const T un = left ? ul : ur;
+    const T p = left ? pl : pr;
+    const T E = left ? El : Er;
+    const bool star = sk != T(0);
+    const T dK = star ? (sK - un) : T(1);
+    const T chi = star ? dK * Num<T>::rcp(sK - ss) : T(1);
+    f[0] = w[0] * un;
+    f[1] = w[1] * un;
+#pragma unroll
+    for (int m = 0; m < ND; ++m) f[2 + m] = rho * w[2 + m] * un + (m == DIR ? p : T(0));
+    f[2 + ND] = (E + p) * un;
+    // star state minus state, times the wave speed of the jump
+    f[0] += sk * (chi * w[0] - w[0]);
+    f[1] += sk * (chi * w[1] - w[1]);
+#pragma unroll
+    for (int m = 0; m < ND; ++m) {
+        T qs = chi * rho * (m == DIR ? ss : w[2 + m]);
+        f[2 + m] += sk * (qs - rho * w[2 + m]);
+    }
+    {
+        T Es = chi * (E + (ss - un) * (rho * ss + p * Num<T>::rcp(dK)));
+        f[2 + ND] += sk * (Es - E);
+    }
+    T uf = un + sk * (chi - T(1));
+    f[NV - 1] = w[3 + ND] * uf;
+    f[NV] = uf;
+}
+
+// K of eq. (var_K) at a cell centre, a2 clamped to [0, 1].
+template <typename T>
+__device__ __forceinline__ T k_coef(const Phys<T>& ph, T a2, T p)
+{
+    T a = fmin(fmax(a2, T(0)), T(1));
+    T b = T(1) - a;
+    T rc1 = ph.gam1 * (p + ph.pc1);
+    T rc2 = ph.gam2 * (p + ph.pc2);
+    T k = a * b * (rc1 - rc2) * Num<T>::rcp(b * rc2 + a * rc1);
+    return (a == T(0) || a == T(1)) ? T(0) : k;
+}
+
+// Running reduction of one thread (CFL speed, QoI, failure counters).
+struct Red {
+    double s_max, p_max;
+    int64_t argmax;
+    int n_nf, n_c2;
+    __device__ __forceinline__ void init() { s_max = 0.0; p_max = -INFINITY; argmax = INT64_MAX; n_nf = 0; n_c2 = 0; }
+    __device__ __forceinline__ void take(double s, double p, int64_t idx)
+    {
+        s_max = fmax(s_max, s);
+        if (p > p_max || (p == p_max && idx < argmax)) { p_max = p; argmax = idx; }
+    }
+    __device__ __forceinline__ void merge(const Red& o)
+    {
+        s_max = fmax(s_max, o.s_max);
+        if (o.p_max > p_max || (o.p_max == p_max && o.argmax < argmax)) { p_max = o.p_max; argmax = o.argmax; }
+        n_nf += o.n_nf;
+        n_c2 += o.n_c2;
+    }
+};
+
+// Accumulate one cell of a new state into the reduction (all in double).
+template <typename T, int ND>
+__device__ __forceinline__ void reduce_cell(const PhysD& ph, const T (&q)[4 + ND], int64_t idx, Red& r)
+{
+    constexpr int NV = 4 + ND;
+    bool finite = true;
+    double qd[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) { qd[v] = (double)q[v]; finite = finite && isfinite(qd[v]); }
+    double rho = qd[0] + qd[1];
+    double ke = 0.0, umax = 0.0;
+#pragma unroll
+    for (int m = 0; m < ND; ++m) {
+        double u = qd[2 + m] / rho;
+        ke += qd[2 + m] * u;
+        umax = fmax(umax, fabs(u));
+    }
+    double a2 = qd[3 + ND];
+    double G = ph.g1inv + a2 * (ph.g2inv - ph.g1inv);
+    double P = ph.pi1 + a2 * (ph.pi2 - ph.pi1);
+    double p = (qd[2 + ND] - 0.5 * ke - P) / G;
+    finite = finite && isfinite(p);
+    if (!finite) { r.n_nf++; return; }
+    double c2 = ((G + 1.0) * p + P) / (G * rho);
+    if (!(rho > 0.0) || !(c2 > 0.0)) { r.n_c2++; return; }
+    r.take(umax + sqrt(c2), p, idx);
+}
+
+// Workgroup-wide merge of the thread reductions; thread 0 writes the tile.
+template <int NT>
+__device__ __forceinline__ void write_partial(Red r, TilePartial* out)
+{
+    __shared__ double s_s[NT / 64], s_p[NT / 64];
+    __shared__ int64_t s_a[NT / 64];
+    __shared__ int s_n[NT / 64], s_c[NT / 64];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        Red o;
+        o.s_max = __shfl_xor(r.s_max, off, 64);
+        o.p_max = __shfl_xor(r.p_max, off, 64);
+        o.argmax = __shfl_xor(r.argmax, off, 64);
+        o.n_nf = __shfl_xor(r.n_nf, off, 64);
+        o.n_c2 = __shfl_xor(r.n_c2, off, 64);
+        r.merge(o);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) { s_s[wave] = r.s_max; s_p[wave] = r.p_max; s_a[wave] = r.argmax; s_n[wave] = r.n_nf; s_c[wave] = r.n_c2; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Red t;
+        t.init();
+        for (int w = 0; w < NT / 64; ++w) {
+            Red o;
+            o.s_max = s_s[w]; o.p_max = s_p[w]; o.argmax = s_a[w]; o.n_nf = s_n[w]; o.n_c2 = s_c[w];
+            t.merge(o);
+        }
+        out->s_max = t.s_max;
+        out->p_max = t.p_max;
+        out->argmax = t.argmax;
+        out->n_nonfinite = t.n_nf;
+        out->n_negc2 = t.n_c2;
+    }
+}
+
+// Map the launch index to a work item so that consecutive tiles of a sample
+// land on the same XCD (workgroups are dealt round-robin to the 8 XCDs; each
+// XCD has its own L2, which then serves the halos of neighbouring tiles).
+__device__ __forceinline__ int xcd_swizzle(int b, int G)
+{
+    const int q = G >> 3, r = G & 7;
+    const int x = b & 7, k = b >> 3;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+__constant__ double c_rk_a[3] = { 0.0, -17.0 / 32.0, -32.0 / 27.0 };
+__constant__ double c_rk_b[3] = { 0.25, 8.0 / 9.0, 0.75 };
+
+// ---------------------------------------------------------------------------
+// Fused right-hand side + low-storage RK stage (+ reduction at stage 3)
+// ---------------------------------------------------------------------------
+template <typename T, int ND, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY)
+stage_kernel(LaunchArgs a, int stage)
+{
+    constexpr int NV = 4 + ND;
+    constexpr int NT = TX * TY;
+    constexpr int HX = TX + 6;
+    constexpr int HY = ND >= 2 ? TY + 6 : 1;
+    constexpr int EXN = TY * (TX + 2);                 // x edge tasks
+    constexpr int EYN = ND >= 2 ? (TY + 2) * TX : 0;   // y edge tasks
+    constexpr int FXN = TY * (TX + 1);
+    constexpr int FYN = ND >= 2 ? (TY + 1) * TX : 0;
+    constexpr int WSZ = NV * HX * HY;
+    constexpr int FSZ = (NV + 1) * (FXN + FYN);
+    constexpr int AL = WSZ > FSZ ? WSZ : FSZ;          // W plane and face fluxes share LDS
+    __shared__ T smem[AL + 2 * NV * (EXN + EYN)];
+    T* sW = smem;                          // [NV][HY][HX]
+    T* sFx = smem;                         // [NV+1][FXN]   (after the edges are built)
+    T* sFy = smem + (NV + 1) * FXN;        // [NV+1][FYN]
+    T* sEm = smem + AL;                    // left edges  [NV][EXN + EYN]
+    T* sEp = sEm + NV * (EXN + EYN);       // right edges [NV][EXN + EYN]
+    constexpr int ES = EXN + EYN;
+
+    const int wi = xcd_swizzle(blockIdx.x, gridDim.x);
+    if (wi >= a.n_work) return;
+    const WorkItem item = a.work[wi];
+    const SampleDesc& d = a.desc[item.sample];
+    SampleState* st = a.state + item.sample;
+    if (st->done) return;
+
+    const Phys<T> ph(a.ph);
+    const int n = d.n;
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    const int ttx = item.tile % d.ntx;
+    const int tty = (item.tile / d.ntx) % d.nty;
+    const int tzc = item.tile / (d.ntx * d.nty);
+    const int x0 = ttx * TX, y0 = tty * TY;
+    const int gx = x0 + tx, gy = y0 + ty;
+    const bool mine = gx < n && (ND < 2 || gy < n);
+    const int64_t ncell = ND == 3 ? (int64_t)n * n * n : (ND == 2 ? (int64_t)n * n : (int64_t)n);
+    const int64_t plane = ND >= 2 ? (int64_t)n * n : (int64_t)n;
+    const T* __restrict__ ua = (const T*)d.buf[a.src];
+    T* __restrict__ ub = (T*)d.buf[a.src ^ 1];
+    T* __restrict__ du = (T*)d.du;
+    const T dt = (T)st->dt;
+    const T ih = (T)(1.0 / d.h);
+    const T rkA = (T)c_rk_a[stage], rkB = (T)c_rk_b[stage];
+    const int bc = a.bc;
+
+    Red red;
+    red.init();
+
+    // load plane gz (with halo) into sW as primitives
+    auto load_plane = [&](int gz) {
+        const int64_t zoff = (int64_t)bc_map(gz, ND == 3 ? n : 1, bc) * plane;
+        for (int e = tid; e < HX * HY; e += NT) {
+            const int hy = e / HX, hx = e % HX;
+            const int cx = bc_map(x0 + hx - 3, n, bc);
+            const int cy = ND >= 2 ? bc_map(y0 + hy - 3, n, bc) : 0;
+            const int64_t idx = zoff + (int64_t)cy * n + cx;
+            T q[NV], w[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) q[v] = ua[v * ncell + idx];
+            to_prim<T, ND>(ph, q, w);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) sW[(v * HY + hy) * HX + hx] = w[v];
+        }
+    };
+
+    // x-y part of the plane now in sW: per-cell sums of the face-flux
+    // differences (F_- - F_+) and of the face-velocity differences (u_+ - u_-)
+    auto plane_xy = [&](T (&xy)[NV + 1]) {
+        // edges along x of cells -1..TX of every row, along y of rows -1..TY
+        for (int e = tid; e < ES; e += NT) {
+            T s[5][NV], lo[NV], hi[NV];
+            if (e < EXN) {
+                const int row = e / (TX + 2), cx = e % (TX + 2) - 1;
+#pragma unroll
+                for (int k = 0; k < 5; ++k)
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) s[k][v] = sW[(v * HY + row + (ND >= 2 ? 3 : 0)) * HX + cx + 1 + k];
+            } else {
+                const int f = e - EXN;
+                const int cy = f / TX - 1, col = f % TX;
+#pragma unroll
+                for (int k = 0; k < 5; ++k)
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) s[k][v] = sW[(v * HY + cy + 1 + k) * HX + col + 3];
+            }
+            cell_edges<T, ND>(ph, s, lo, hi);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) { sEm[v * ES + e] = lo[v]; sEp[v * ES + e] = hi[v]; }
+        }
+        __syncthreads();
+        // faces: x faces i-1/2 (i = 0..TX) of every row, y faces j-1/2
+        for (int f = tid; f < FXN + FYN; f += NT) {
+            T wl[NV], wr[NV], fl[NV + 1];
+            if (f < FXN) {
+                const int row = f / (TX + 1), i = f % (TX + 1);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    wl[v] = sEp[v * ES + row * (TX + 2) + i];
+                    wr[v] = sEm[v * ES + row * (TX + 2) + i + 1];
+                }
+                hllc<T, ND, 0>(ph, wl, wr, fl);
+#pragma unroll
+                for (int v = 0; v <= NV; ++v) sFx[v * FXN + f] = fl[v];
+            } else {
+                if constexpr (ND >= 2) {
+                    const int g = f - FXN;
+                    const int j = g / TX, col = g % TX;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        wl[v] = sEp[v * ES + EXN + j * TX + col];
+                        wr[v] = sEm[v * ES + EXN + (j + 1) * TX + col];
+                    }
+                    hllc<T, ND, 1 < ND ? 1 : 0>(ph, wl, wr, fl);
+#pragma unroll
+                    for (int v = 0; v <= NV; ++v) sFy[v * FYN + g] = fl[v];
+                }
+            }
+        }
+        __syncthreads();
+        const int fx = ty * (TX + 1) + tx;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) xy[v] = sFx[v * FXN + fx] - sFx[v * FXN + fx + 1];
+        xy[NV] = sFx[NV * FXN + fx + 1] - sFx[NV * FXN + fx];
+        if constexpr (ND >= 2) {
+            const int fy = ty * TX + tx;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) xy[v] += sFy[v * FYN + fy] - sFy[v * FYN + fy + TX];
+            xy[NV] += sFy[NV * FYN + fy + TX] - sFy[NV * FYN + fy];
+        }
+    };
+
+    // finish one cell: L(U) from the flux-difference sums, then the stage
+    auto finish = [&](int64_t idx, const T (&sum)[NV + 1], const T (&wc)[NV]) {
+        T L[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) L[v] = sum[v] * ih;
+        L[NV - 1] += (wc[3 + ND] + k_coef<T>(ph, wc[3 + ND], wc[2 + ND])) * (sum[NV] * ih);
+        T qn[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int64_t o = v * ncell + idx;
+            T dv = dt * L[v];
+            if (stage > 0) dv += rkA * du[o];
+            if (stage < 2) du[o] = dv;
+            qn[v] = ua[o] + rkB * dv;
+            ub[o] = qn[v];
+        }
+        if (stage == 2) reduce_cell<T, ND>(a.ph, qn, idx, red);
+    };
+
+    if constexpr (ND <= 2) {
+        load_plane(0);
+        __syncthreads();
+        T xy[NV + 1];
+        T wc[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) wc[v] = sW[(v * HY + ty + (ND >= 2 ? 3 : 0)) * HX + tx + 3];
+        plane_xy(xy);
+        if (mine) finish((ND == 2 ? (int64_t)gy * n : 0) + gx, xy, wc);
+    } else {
+        const int z0 = tzc * a.zchunk;
+        const int z1 = min(z0 + a.zchunk, n) - 1;      // last plane of the chunk
+        T q[5][NV];                                    // primitives of planes p-4..p
+        T pend[3][NV + 1];                             // x-y sums of planes p-3..p-1
+        T ep_prev[NV];                                 // upper z edge of cell p-3
+        T fz_lo[NV + 1];                               // lower z face of cell p-3
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int v = 0; v <= NV; ++v) pend[k][v] = T(0);
+        const int cxg = min(gx, n - 1), cyg = min(gy, n - 1);
+        for (int p = z0 - 3; p <= z1 + 3; ++p) {
+            const bool out = p >= z0 && p <= z1;
+            T wn[NV];
+            T xy[NV + 1];
+            if (out) {
+                __syncthreads();
+                load_plane(p);
+                __syncthreads();
+#pragma unroll
+                for (int v = 0; v < NV; ++v) wn[v] = sW[(v * HY + ty + 3) * HX + tx + 3];
+                plane_xy(xy);
+            } else {
+                const int64_t idx = (int64_t)bc_map(p, n, bc) * plane + (int64_t)cyg * n + cxg;
+                T qq[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) qq[v] = ua[v * ncell + idx];
+                to_prim<T, ND>(ph, qq, wn);
+#pragma unroll
+                for (int v = 0; v <= NV; ++v) xy[v] = T(0);
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) q[k][v] = q[k + 1][v];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) q[4][v] = wn[v];
+            if (p >= z0 + 1) {
+                // z edges of cell p-2
+                T lo[NV], hi[NV];
+                cell_edges<T, ND>(ph, q, lo, hi);
+                if (p >= z0 + 2) {
+                    // face between p-3 and p-2
+                    T fz[NV + 1];
+                    hllc<T, ND, ND - 1>(ph, ep_prev, lo, fz);
+                    if (p >= z0 + 3 && mine) {
+                        T sum[NV + 1];
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) sum[v] = pend[0][v] + (fz_lo[v] - fz[v]);
+                        sum[NV] = pend[0][NV] + (fz[NV] - fz_lo[NV]);
+                        T wc[NV];
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) wc[v] = q[1][v];
+                        finish((int64_t)(p - 3) * plane + (int64_t)gy * n + gx, sum, wc);
+                    }
+#pragma unroll
+                    for (int v = 0; v <= NV; ++v) fz_lo[v] = fz[v];
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v) ep_prev[v] = hi[v];
+            }
+#pragma unroll
+            for (int v = 0; v <= NV; ++v) { pend[0][v] = pend[1][v]; pend[1][v] = pend[2][v]; pend[2][v] = xy[v]; }
+        }
+    }
+    if (stage == 2) write_partial<NT>(red, a.part + d.tile0 + item.tile);
+}
+
+// ---------------------------------------------------------------------------
+// Reduction of a state without stepping (initial level)
+// ---------------------------------------------------------------------------
+template <typename T, int ND, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) reduce_kernel(LaunchArgs a)
+{
+    constexpr int NV = 4 + ND;
+    const int wi = xcd_swizzle(blockIdx.x, gridDim.x);
+    if (wi >= a.n_work) return;
+    const WorkItem item = a.work[wi];
+    const SampleDesc& d = a.desc[item.sample];
+    if (a.state[item.sample].done) return;
+    const int n = d.n;
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int ttx = item.tile % d.ntx, tty = (item.tile / d.ntx) % d.nty, tzc = item.tile / (d.ntx * d.nty);
+    const int gx = ttx * TX + tx, gy = tty * TY + ty;
+    const int64_t ncell = ND == 3 ? (int64_t)n * n * n : (ND == 2 ? (int64_t)n * n : (int64_t)n);
+    const int64_t plane = ND >= 2 ? (int64_t)n * n : (int64_t)n;
+    const T* u = (const T*)d.buf[a.src];
+    Red red;
+    red.init();
+    if (gx < n && (ND < 2 || gy < n)) {
+        const int z0 = ND == 3 ? tzc * a.zchunk : 0;
+        const int z1 = ND == 3 ? min(z0 + a.zchunk, n) : 1;
+        for (int z = z0; z < z1; ++z) {
+            const int64_t idx = (int64_t)z * plane + (ND >= 2 ? (int64_t)gy * n : 0) + gx;
+            T q[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) q[v] = u[v * ncell + idx];
+            reduce_cell<T, ND>(a.ph, q, idx, red);
+        }
+    }
+    write_partial<TX * TY>(red, a.part + d.tile0 + item.tile);
+}
+
+// ---------------------------------------------------------------------------
+// Per-sample finalisation of a step: time, QoI, status, next dt
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) finalize_kernel(const SampleDesc* desc, SampleState* state,
+                                                       const TilePartial* part, int initial, double* dt_log,
+                                                       int64_t dt_log_len)
+{
+    const SampleDesc& d = desc[blockIdx.x];
+    SampleState& st = state[blockIdx.x];
+    if (st.done) return;
+    Red r;
+    r.init();
+    for (int t = threadIdx.x; t < d.ntiles; t += 256) {
+        const TilePartial& tp = part[d.tile0 + t];
+        Red o;
+        o.s_max = tp.s_max; o.p_max = tp.p_max; o.argmax = tp.argmax; o.n_nf = tp.n_nonfinite; o.n_c2 = tp.n_negc2;
+        r.merge(o);
+    }
+    __shared__ double s_s[4], s_p[4];
+    __shared__ int64_t s_a[4];
+    __shared__ int s_n[4], s_c[4];
+    for (int off = 32; off >= 1; off >>= 1) {
+        Red o;
+        o.s_max = __shfl_xor(r.s_max, off, 64);
+        o.p_max = __shfl_xor(r.p_max, off, 64);
+        o.argmax = __shfl_xor(r.argmax, off, 64);
+        o.n_nf = __shfl_xor(r.n_nf, off, 64);
+        o.n_c2 = __shfl_xor(r.n_c2, off, 64);
+        r.merge(o);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) { s_s[wave] = r.s_max; s_p[wave] = r.p_max; s_a[wave] = r.argmax; s_n[wave] = r.n_nf; s_c[wave] = r.n_c2; }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    Red t;
+    t.init();
+    for (int w = 0; w < 4; ++w) {
+        Red o;
+        o.s_max = s_s[w]; o.p_max = s_p[w]; o.argmax = s_a[w]; o.n_nf = s_n[w]; o.n_c2 = s_c[w];
+        t.merge(o);
+    }
+    if (!initial) {
+        st.t = st.last ? d.t_end : st.t + st.dt;
+        st.steps += 1;
+    }
+    if (initial) {
+        st.p_max = t.p_max;
+        st.argmax = t.argmax;
+        st.t_at_max = st.t;
+    }
+    if (t.n_nf > 0) { st.status = OFM_SAMPLE_NONFINITE; st.done = 1; return; }
+    if (t.n_c2 > 0) { st.status = OFM_SAMPLE_NEGATIVE_C2; st.done = 1; return; }
+    if (!initial && t.p_max > st.p_max) {
+        st.p_max = t.p_max;
+        st.argmax = t.argmax;
+        st.t_at_max = st.t;
+    }
+    const bool fin = d.n_steps > 0 ? st.steps >= d.n_steps : st.t >= d.t_end;
+    if (fin) { st.done = 1; return; }
+    if (st.steps >= d.max_steps) { st.status = OFM_SAMPLE_MAX_STEPS; st.done = 1; return; }
+    double dt = d.cfl * d.h / t.s_max;
+    st.last = 0;
+    if (d.n_steps <= 0 && dt >= d.t_end - st.t) { dt = d.t_end - st.t; st.last = 1; }
+    st.dt = dt;
+    if (dt_log && st.steps < dt_log_len) dt_log[st.steps] = dt;
+}
+
+// ---------------------------------------------------------------------------
+// Initial state of a cloud (one sample per launch)
+// ---------------------------------------------------------------------------
+struct InitArgs {
+    PhysD ph;
+    const double* bubbles;   // nb x 4
+    int32_t nb;
+    int32_t n, n_sub;
+    double rho1, rho2, p_bubble, p_inf;
+    double cx, cy, cz, radius, delta, width;
+    void* u;
+};
+
+// Workgroup = 256 cells (8x8x4 in 3-D, 16x16 in 2-D, 256 in 1-D).  The
+// bubbles are culled against the workgroup's box in chunks of 256 through
+// LDS; each thread keeps a bit mask of its sub-samples found inside.  Inside
+// tests are in double without contraction, as |x - c|^2 < r^2.
+template <typename T, int ND>
+__global__ void __launch_bounds__(256) init_kernel(InitArgs a)
+{
+#pragma clang fp contract(off)
+    constexpr int BX = ND == 3 ? 8 : (ND == 2 ? 16 : 256);
+    constexpr int BY = ND == 3 ? 8 : (ND == 2 ? 16 : 1);
+    constexpr int BZ = ND == 3 ? 4 : 1;
+    const int n = a.n;
+    const int nbx = (n + BX - 1) / BX, nby = ND >= 2 ? (n + BY - 1) / BY : 1;
+    const int b = blockIdx.x;
+    const int bx = b % nbx, by = (b / nbx) % nby, bz = b / (nbx * nby);
+    const int tid = threadIdx.x;
+    const int i = bx * BX + tid % BX;
+    const int j = ND >= 2 ? by * BY + (tid / BX) % BY : 0;
+    const int k = ND == 3 ? bz * BZ + tid / (BX * BY) : 0;
+    const double N = (double)n;
+    // workgroup box with a margin, for culling
+    const double m = 1e-9;
+    const double lx = (double)(bx * BX) / N - m, hx = (double)(bx * BX + BX) / N + m;
+    const double ly = (double)(by * BY) / N - m, hy = (double)(by * BY + BY) / N + m;
+    const double lz = (double)(bz * BZ) / N - m, hz = (double)(bz * BZ + BZ) / N + m;
+    __shared__ double sb[256][4];
+    __shared__ int s_cnt;
+    const int ns = a.n_sub;
+    const int nsz = ND == 3 ? ns : 1, nsy = ND >= 2 ? ns : 1;
+    uint64_t mask = 0;
+    const double den = (double)((int64_t)ns * n);
+    for (int c0 = 0; c0 < a.nb; c0 += 256) {
+        if (tid == 0) s_cnt = 0;
+        __syncthreads();
+        const int bi = c0 + tid;
+        if (bi < a.nb) {
+            const double* q = a.bubbles + 4 * bi;
+            bool hit = q[0] + q[3] >= lx && q[0] - q[3] <= hx;
+            if (ND >= 2) hit = hit && q[1] + q[3] >= ly && q[1] - q[3] <= hy;
+            if (ND == 3) hit = hit && q[2] + q[3] >= lz && q[2] - q[3] <= hz;
+            if (hit) {
+                const int slot = atomicAdd(&s_cnt, 1);
+                sb[slot][0] = q[0]; sb[slot][1] = q[1]; sb[slot][2] = q[2]; sb[slot][3] = q[3];
+            }
+        }
+        __syncthreads();
+        const int cnt = s_cnt;
+        if (i < n && j < (ND >= 2 ? n : 1) && k < (ND == 3 ? n : 1)) {
+            for (int t = 0; t < cnt; ++t) {
+                const double bxc = sb[t][0], byc = sb[t][1], bzc = sb[t][2], r = sb[t][3];
+                const double r2 = r * r;
+                int bit = 0;
+                for (int sc = 0; sc < nsz; ++sc)
+                    for (int sbb = 0; sbb < nsy; ++sbb)
+                        for (int sa = 0; sa < ns; ++sa, ++bit) {
+                            const double px = ((double)((int64_t)ns * i + sa) + 0.5) / den;
+                            const double dx = px - bxc;
+                            double d2 = dx * dx;
+                            if (ND >= 2) {
+                                const double py = ((double)((int64_t)ns * j + sbb) + 0.5) / den;
+                                const double dy = py - byc;
+                                d2 = d2 + dy * dy;
+                            }
+                            if (ND == 3) {
+                                const double pz = ((double)((int64_t)ns * k + sc) + 0.5) / den;
+                                const double dz = pz - bzc;
+                                d2 = d2 + dz * dz;
+                            }
+                            if (d2 < r2) mask |= (uint64_t)1 << bit;
+                        }
+            }
+        }
+        __syncthreads();
+    }
+    if (!(i < n && j < (ND >= 2 ? n : 1) && k < (ND == 3 ? n : 1))) return;
+    const int ntot = ns * nsy * nsz;
+    const double a2 = (double)__popcll(mask) / (double)ntot;
+    double ccx = ((double)i + 0.5) / N - a.cx;
+    double rr = ccx * ccx;
+    if (ND >= 2) { const double ccy = ((double)j + 0.5) / N - a.cy; rr = rr + ccy * ccy; }
+    if (ND == 3) { const double ccz = ((double)k + 0.5) / N - a.cz; rr = rr + ccz * ccz; }
+    const double rad = sqrt(rr);
+    double s = (rad - a.radius - a.delta) / a.width;
+    s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
+    const double p = a.p_bubble + (a.p_inf - a.p_bubble) * (s * s * (3.0 - 2.0 * s));
+    const double G = a.ph.g1inv + a2 * (a.ph.g2inv - a.ph.g1inv);
+    const double P = a.ph.pi1 + a2 * (a.ph.pi2 - a.ph.pi1);
+    const int64_t ncell = ND == 3 ? (int64_t)n * n * n : (ND == 2 ? (int64_t)n * n : (int64_t)n);
+    const int64_t idx = ((int64_t)k * (ND >= 2 ? n : 1) + j) * n + i;
+    T* u = (T*)a.u;
+    constexpr int NV = 4 + ND;
+    u[0 * ncell + idx] = (T)((1.0 - a2) * a.rho1);
+    u[1 * ncell + idx] = (T)(a2 * a.rho2);
+#pragma unroll
+    for (int mm = 0; mm < ND; ++mm) u[(2 + mm) * ncell + idx] = (T)0;
+    u[(2 + ND) * ncell + idx] = (T)(G * p + P);
+    u[(NV - 1) * ncell + idx] = (T)a2;
+}
+
+// Primitive -> conserved (test states), element-wise.
+template <typename T, int ND>
+__global__ void __launch_bounds__(256) prim_to_cons_kernel(PhysD phd, const T* w, T* u, int64_t ncell)
+{
+    constexpr int NV = 4 + ND;
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= ncell) return;
+    const Phys<T> ph(phd);
+    T wv[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) wv[v] = w[v * ncell + c];
+    const T rho = wv[0] + wv[1];
+    T ke = T(0);
+    u[c] = wv[0];
+    u[ncell + c] = wv[1];
+#pragma unroll
+    for (int m = 0; m < ND; ++m) {
+        u[(2 + m) * ncell + c] = rho * wv[2 + m];
+        ke += rho * wv[2 + m] * wv[2 + m];
+    }
+    const T a2 = wv[3 + ND];
+    u[(2 + ND) * ncell + c] = ph.gamma(a2) * wv[2 + ND] + ph.pinf(a2) + T(0.5) * ke;
+    u[(3 + ND) * ncell + c] = a2;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+template <typename T, int ND, int TX, int TY>
+static hipError_t launch_stage_t(const LaunchArgs& a, int stage, hipStream_t s)
+{
+    hipLaunchKernelGGL((stage_kernel<T, ND, TX, TY>), dim3(a.n_work), dim3(TX * TY), 0, s, a, stage);
+    return hipGetLastError();
+}
+
+template <typename T, int ND, int TX, int TY>
+static hipError_t launch_reduce_t(const LaunchArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL((reduce_kernel<T, ND, TX, TY>), dim3(a.n_work), dim3(TX * TY), 0, s, a);
+    return hipGetLastError();
+}
+
+// Tile shapes compiled for each (precision, dimension).
+#define OFM_FOR_TILES(X)                                                        \
+    X(float, 3, 16, 16) X(float, 3, 32, 8) X(float, 3, 16, 8)                  \
+    X(double, 3, 16, 8) X(double, 3, 16, 16) X(double, 3, 8, 8)                \
+    X(float, 2, 16, 16) X(float, 2, 32, 8) X(double, 2, 16, 16) X(double, 2, 16, 8) \
+    X(float, 1, 256, 1) X(double, 1, 256, 1) X(float, 1, 64, 1) X(double, 1, 64, 1)
+
+bool tile_supported(int precision, int ndim, int tx, int ty)
+{
+#define X(T, ND, TX, TY) \
+    if ((precision == OFM_F64) == (sizeof(T) == 8) && ndim == ND && tx == TX && ty == TY) return true;
+    OFM_FOR_TILES(X)
+#undef X
+    return false;
+}
+
+hipError_t launch_stage(int precision, int ndim, int tx, int ty, const LaunchArgs& a, int stage, hipStream_t s)
+{
+#define X(T, ND, TX, TY) \
+    if ((precision == OFM_F64) == (sizeof(T) == 8) && ndim == ND && tx == TX && ty == TY) return launch_stage_t<T, ND, TX, TY>(a, stage, s);
+    OFM_FOR_TILES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce(int precision, int ndim, int tx, int ty, const LaunchArgs& a, hipStream_t s)
+{
+#define X(T, ND, TX, TY) \
+    if ((precision == OFM_F64) == (sizeof(T) == 8) && ndim == ND && tx == TX && ty == TY) return launch_reduce_t<T, ND, TX, TY>(a, s);
+    OFM_FOR_TILES(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_finalize(const SampleDesc* desc, SampleState* state, const TilePartial* part, int n_samples,
+                           int initial, double* dt_log, int64_t dt_log_len, hipStream_t s)
+{
+    hipLaunchKernelGGL(finalize_kernel, dim3(n_samples), dim3(256), 0, s, desc, state, part, initial, dt_log, dt_log_len);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(int precision, int ndim, const InitLaunch& L, hipStream_t s)
+{
+    InitArgs a;
+    a.ph = L.ph;
+    a.bubbles = L.bubbles;
+    a.nb = L.nb;
+    a.n = L.n;
+    a.n_sub = L.n_sub;
+    a.rho1 = L.rho1; a.rho2 = L.rho2; a.p_bubble = L.p_bubble; a.p_inf = L.p_inf;
+    a.cx = L.center[0]; a.cy = L.center[1]; a.cz = L.center[2];
+    a.radius = L.radius; a.delta = L.delta; a.width = L.width;
+    a.u = L.u;
+    const int n = L.n;
+    int blocks;
+    if (ndim == 3) blocks = ((n + 7) / 8) * ((n + 7) / 8) * ((n + 3) / 4);
+    else if (ndim == 2) blocks = ((n + 15) / 16) * ((n + 15) / 16);
+    else blocks = (n + 255) / 256;
+#define IL(T, ND) hipLaunchKernelGGL((init_kernel<T, ND>), dim3(blocks), dim3(256), 0, s, a)
+    if (precision == OFM_F64) {
+        if (ndim == 3) IL(double, 3); else if (ndim == 2) IL(double, 2); else IL(double, 1);
+    } else {
+        if (ndim == 3) IL(float, 3); else if (ndim == 2) IL(float, 2); else IL(float, 1);
+    }
+#undef IL
+    return hipGetLastError();
+}
+
+hipError_t launch_prim_to_cons(int precision, int ndim, const PhysD& ph, const void* w, void* u, int64_t ncell,
+                               hipStream_t s)
+{
+    const int blocks = (int)((ncell + 255) / 256);
+#define PL(T, ND) hipLaunchKernelGGL((prim_to_cons_kernel<T, ND>), dim3(blocks), dim3(256), 0, s, ph, (const T*)w, (T*)u, ncell)
+    if (precision == OFM_F64) {
+        if (ndim == 3) PL(double, 3); else if (ndim == 2) PL(double, 2); else PL(double, 1);
+    } else {
+        if (ndim == 3) PL(float, 3); else if (ndim == 2) PL(float, 2); else PL(float, 1);
+    }
+#undef PL
+    return hipGetLastError();
+}
+
+}  // namespace ofm

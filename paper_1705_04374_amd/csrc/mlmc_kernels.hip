@@ -1,0 +1,194 @@
+// OF-MLMC estimator kernels (Sukys et al., arXiv:1705.04374, Sec. 2.4.3-2.4.4),
+// all in double on the device.  The statistics are tiny next to the solves
+// (Appendix A.3 notes the coefficient system is never a bottleneck), so each
+// call is one workgroup; what matters is that the sums are deterministic
+// (fixed-order strided partial sums, then a fixed tree) and stay on the GPU.
+#include "flow_kernels.h"
+
+#include <math.h>
+
+namespace ofm {
+
+constexpr int MT = 256;
+
+// Fixed-order workgroup sum of one double per thread.
+__device__ double block_sum(double v, double* sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = MT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// Moments of one term: (M_used, mean_f, mean_c, Var_f, Var_c, Cov), two-pass.
+__global__ void __launch_bounds__(MT) moments_kernel(const double* qf, const double* qc, const int32_t* ok,
+                                                     int64_t M, double* out)
+{
+    __shared__ double sh[MT];
+    double cnt = 0.0, sf = 0.0, sc = 0.0;
+    for (int64_t i = threadIdx.x; i < M; i += MT) {
+        if (ok && ok[i] == 0) continue;
+        cnt += 1.0;
+        sf += qf[i];
+        if (qc) sc += qc[i];
+    }
+    const double m = block_sum(cnt, sh);
+    const double mf = m > 0.0 ? block_sum(sf, sh) / m : 0.0;
+    const double mc = (m > 0.0 && qc) ? block_sum(sc, sh) / m : 0.0;
+    double vf = 0.0, vc = 0.0, cv = 0.0;
+    for (int64_t i = threadIdx.x; i < M; i += MT) {
+        if (ok && ok[i] == 0) continue;
+        const double df = qf[i] - mf;
+        vf += df * df;
+        if (qc) {
+            const double dc = qc[i] - mc;
+            vc += dc * dc;
+            cv += df * dc;
+        }
+    }
+    vf = block_sum(vf, sh);
+    vc = block_sum(vc, sh);
+    cv = block_sum(cv, sh);
+    if (threadIdx.x == 0) {
+        out[0] = m;
+        out[1] = mf;
+        out[2] = mc;
+        const bool two = m >= 2.0;
+        out[3] = two ? vf / (m - 1.0) : 0.0;
+        out[4] = two && qc ? vc / (m - 1.0) : 0.0;
+        out[5] = two && qc ? cv / (m - 1.0) : 0.0;
+    }
+}
+
+// Tridiagonal system of eq. (alpha-matvec), generalised to per-term
+// estimates: row k is the derivative of the estimated cost
+// sum_l W_l Var(alpha_l q_f,l - alpha_{l-1} q_c,l) with respect to alpha_k.
+// Thomas algorithm; a non-positive pivot means the estimates are not
+// positive definite -> flag OFM_ESINGULAR and alpha = 1 (classical MLMC).
+__global__ void coefficients_kernel(int L, const double* mom, const double* W, double* alpha, int32_t* flag)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double cp[32], dp[32];
+    int bad = 0;
+    for (int k = 0; k < L; ++k) {
+        const double diag = mom[6 * k + 3] * W[k] + mom[6 * (k + 1) + 4] * W[k + 1];
+        const double low = k >= 1 ? -mom[6 * k + 5] * W[k] : 0.0;
+        const double up = k + 1 <= L - 1 ? -mom[6 * (k + 1) + 5] * W[k + 1] : 0.0;
+        const double rhs = k == L - 1 ? mom[6 * L + 5] * W[L] : 0.0;
+        const double piv = diag - (k >= 1 ? low * cp[k - 1] : 0.0);
+        if (!(piv > 0.0) || fabs(piv) < 1e-300) { bad = 1; break; }
+        cp[k] = up / piv;
+        dp[k] = (rhs - (k >= 1 ? low * dp[k - 1] : 0.0)) / piv;
+    }
+    alpha[L] = 1.0;
+    if (bad) {
+        for (int k = 0; k < L; ++k) alpha[k] = 1.0;
+        *flag = OFM_ESINGULAR;
+        return;
+    }
+    for (int k = L - 1; k >= 0; --k) alpha[k] = dp[k] - (k + 1 <= L - 1 ? cp[k] * alpha[k + 1] : 0.0);
+    *flag = 0;
+}
+
+// eq. (ocv-mlmc-err): per-term variances of the weighted differences and
+// the squared sampling error.
+__global__ void errors_kernel(int L, const double* mom, const double* alpha, double* sig, double* eps2)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double e = 0.0;
+    for (int l = 0; l <= L; ++l) {
+        const double* m = mom + 6 * l;
+        double s = alpha[l] * alpha[l] * m[3];
+        if (l >= 1) s += alpha[l - 1] * alpha[l - 1] * m[4] - 2.0 * alpha[l] * alpha[l - 1] * m[5];
+        sig[l] = s;
+        e += s / m[0];
+    }
+    *eps2 = e;
+}
+
+// eq. (ocv-mlmc): the estimator.
+__global__ void estimate_kernel(int L, const double* mom, const double* alpha, double* E)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double e = alpha[0] * mom[1];
+    for (int l = 1; l <= L; ++l) e += alpha[l] * mom[6 * l + 1] - alpha[l - 1] * mom[6 * l + 2];
+    *E = e;
+}
+
+// eq. (M-tol) / eq. (M-budget) with the keep-computed-samples loop of step 7.
+__global__ void optimal_M_kernel(int L, const double* sig, const double* W, const int64_t* have, int mode,
+                                 double target, int64_t* out, int32_t* flag)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    bool fixed[32];
+    int64_t M[32];
+    for (int l = 0; l <= L; ++l) { fixed[l] = false; M[l] = have[l]; }
+    *flag = 0;
+    for (int it = 0; it <= L + 1; ++it) {
+        double rest = mode == OFM_MODE_TOLERANCE ? target * target : target;
+        double S = 0.0;
+        for (int l = 0; l <= L; ++l) {
+            if (fixed[l]) rest -= mode == OFM_MODE_TOLERANCE ? sig[l] / (double)have[l] : (double)have[l] * W[l];
+            else S += sqrt(sig[l] * W[l]);
+        }
+        if (mode == OFM_MODE_TOLERANCE && !(rest > 0.0)) {
+            *flag = OFM_EINFEASIBLE;
+            for (int l = 0; l <= L; ++l) out[l] = have[l];
+            return;
+        }
+        for (int l = 0; l <= L; ++l) {
+            if (fixed[l]) continue;
+            double m;
+            if (mode == OFM_MODE_TOLERANCE) m = ceil(sqrt(sig[l] / W[l]) * S / rest);
+            else m = (rest > 0.0 && S > 0.0) ? ceil(rest * sqrt(sig[l] / W[l]) / S) : 0.0;
+            M[l] = (int64_t)m;
+        }
+        bool changed = false;
+        for (int l = 0; l <= L; ++l) {
+            if (!fixed[l] && M[l] < have[l]) { M[l] = have[l]; fixed[l] = true; changed = true; }
+        }
+        bool any_free = false;
+        for (int l = 0; l <= L; ++l) any_free = any_free || !fixed[l];
+        if (!changed || !any_free) break;
+    }
+    for (int l = 0; l <= L; ++l) out[l] = fixed[l] ? have[l] : M[l];
+}
+
+hipError_t launch_moments(const double* qf, const double* qc, const int32_t* ok, int64_t M, double* out,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(moments_kernel, dim3(1), dim3(MT), 0, s, qf, qc, ok, M, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_coefficients(int L, const double* mom, const double* W, double* alpha, int32_t* flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(coefficients_kernel, dim3(1), dim3(64), 0, s, L, mom, W, alpha, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_errors(int L, const double* mom, const double* alpha, double* sig, double* eps2, hipStream_t s)
+{
+    hipLaunchKernelGGL(errors_kernel, dim3(1), dim3(64), 0, s, L, mom, alpha, sig, eps2);
+    return hipGetLastError();
+}
+
+hipError_t launch_estimate(int L, const double* mom, const double* alpha, double* E, hipStream_t s)
+{
+    hipLaunchKernelGGL(estimate_kernel, dim3(1), dim3(64), 0, s, L, mom, alpha, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_optimal_M(int L, const double* sig, const double* W, const int64_t* have, int mode, double target,
+                            int64_t* out, int32_t* flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(optimal_M_kernel, dim3(1), dim3(64), 0, s, L, sig, W, have, mode, target, out, flag);
+    return hipGetLastError();
+}
+
+}  // namespace ofm

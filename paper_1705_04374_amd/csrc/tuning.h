@@ -1,0 +1,55 @@
+// Tile / schedule choice of the stage kernel per (precision, dimension, size).
+// Defaults are set here; ofm_tune_set overrides one entry (the measuring
+// autotuner lives in the Python driver, which times candidates through the
+// library itself and stores the winners).
+#pragma once
+
+#include <map>
+#include <tuple>
+
+namespace ofm {
+
+struct TileChoice {
+    int tx, ty, zchunk, graph_steps;
+};
+
+struct Tuning {
+    // key: (precision, ndim, size class = ceil(log2 n))
+    std::map<std::tuple<int, int, int>, TileChoice> table;
+
+    static int size_class(int n)
+    {
+        int c = 0;
+        while ((1 << c) < n) ++c;
+        return c;
+    }
+
+    TileChoice choose(int precision, int ndim, int maxn, int /*n_samples*/) const
+    {
+        auto it = table.find(std::make_tuple(precision, ndim, size_class(maxn)));
+        if (it != table.end()) return it->second;
+        TileChoice t;
+        if (ndim == 3) {
+            t.tx = 16;
+            t.ty = precision == 1 ? 8 : 16;
+            t.zchunk = maxn >= 256 ? 32 : 16;
+        } else if (ndim == 2) {
+            t.tx = 16;
+            t.ty = 16;
+            t.zchunk = 1;
+        } else {
+            t.tx = 256;
+            t.ty = 1;
+            t.zchunk = 1;
+        }
+        t.graph_steps = maxn >= 256 ? 4 : 16;
+        return t;
+    }
+
+    void set(int precision, int ndim, int n, const TileChoice& t)
+    {
+        table[std::make_tuple(precision, ndim, size_class(n))] = t;
+    }
+};
+
+}  // namespace ofm

@@ -1,0 +1,238 @@
+"""GPU parity of the solver against the oracle, through the C ABI.
+
+Tolerances (fixed by the method's arithmetic, see the design notes):
+  FP64: per-variable max |gpu - oracle| / max |oracle| <= 1e-10 after 100
+        steps; step sizes to 1e-12 relative; QoI value to 1e-10.
+  FP32: per-variable relative L1 <= 1e-4 and p_max within 0.5 % after 100
+        steps (stencil in float, QoI and step size in double).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle.flow as OF
+from oracle.sampler import sample_cloud
+from workloads.configs import (BASE, EOS, MASTER_SEED, cloud_spec, interface_primitives,
+                               riemann_primitives, solver_config)
+from helpers import alloc_state, max_rel_field, oracle_shape, read_state, rel_l1
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1705_04374_amd import capi
+    assert torch.cuda.is_available()
+    c = capi.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_run(ctx, cfg, precision, bubbles=None, W=None, n_steps=0, tune=None):
+    """Initial state (cloud or primitives) then n_steps steps on the GPU."""
+    import torch
+    from paper_1705_04374_amd import capi
+    if tune:
+        capi.ofm_tune_set(ctx, capi.OFM_F64 if precision == "f64" else capi.OFM_F32, cfg["ndim"], cfg["n"], *tune)
+    spec = capi.make_spec(cfg, precision, n_steps=max(n_steps, 1))
+    st, bufs = alloc_state(cfg, precision)
+    if W is not None:
+        dt = torch.float64 if precision == "f64" else torch.float32
+        w = torch.tensor(W.reshape(W.shape[0], -1), dtype=dt, device="cuda").contiguous()
+        capi.ofm_state_from_primitive(ctx, spec, w, st)
+    else:
+        capi.ofm_state_init(ctx, spec, bubbles, st)
+    q, dts = (None, np.zeros(0))
+    if n_steps:
+        q, dts = capi.ofm_step(ctx, spec, st, n_steps)
+    return read_state(st, bufs), q, dts
+
+
+# --------------------------------------------------------------------------
+# initial state
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("cloud,n", [("cloud2d", 40), ("cloud50", 24), ("cloud500", 40)])
+def test_init_matches_oracle(ctx, cloud, n):
+    say("init", cloud, n)
+    cfg = solver_config(cloud, n)
+    bub = sample_cloud(cloud_spec(cloud), MASTER_SEED, 0, 3)
+    U, _, _ = gpu_run(ctx, cfg, "f64", bubbles=bub)
+    R = OF.init_state(cfg, bub)
+    U = oracle_shape(cfg, U)
+    nd = cfg["ndim"]
+    assert np.array_equal(U[3 + nd], R[3 + nd])          # a2: exact sub-sample counts
+    assert np.all(max_rel_field(U, R) <= 1e-15)
+
+
+# --------------------------------------------------------------------------
+# FP64 parity after 100 steps
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("cloud,n", [("cloud2d", 48), ("cloud50", 24)])
+def test_fp64_cloud_100_steps(ctx, cloud, n):
+    say("fp64 100 steps", cloud, n)
+    cfg = solver_config(cloud, n)
+    bub = sample_cloud(cloud_spec(cloud), MASTER_SEED, 0, 1)
+    U, q, dts = gpu_run(ctx, cfg, "f64", bubbles=bub, n_steps=100)
+    R0 = OF.init_state(cfg, bub)
+    R, rdts = OF.run_steps(cfg, R0, 100)
+    np.testing.assert_allclose(dts, rdts, rtol=1e-12, atol=0)
+    err = max_rel_field(oracle_shape(cfg, U), R)
+    assert np.all(err <= 1e-10), err
+    ref = OF.solve(cfg, bub, n_steps=100)
+    assert q["status"] == 0 and q["steps"] == 100
+    assert math.isclose(q["p_max"], ref["p_max"], rel_tol=1e-10)
+    assert q["argmax"] == ref["argmax"]
+
+
+def test_fp64_ragged_tiles_and_chunks(ctx):
+    """n = 20 leaves ragged tiles in x, y and z for every tile shape."""
+    say("fp64 ragged 20^3")
+    cfg = solver_config("cloud50", 20)
+    bub = sample_cloud(cloud_spec("cloud50"), MASTER_SEED, 0, 2)
+    R, _ = OF.run_steps(cfg, OF.init_state(cfg, bub), 12)
+    for tune in [(16, 8, 16, 2), (8, 8, 7, 2), (16, 16, 32, 2)]:
+        U, _, _ = gpu_run(ctx, cfg, "f64", bubbles=bub, n_steps=12, tune=tune)
+        assert np.all(max_rel_field(oracle_shape(cfg, U), R) <= 1e-11), tune
+
+
+def test_fp64_tiling_invariance_bitwise(ctx):
+    """Per-cell arithmetic does not depend on the tiling: every compiled tile
+    shape and z-chunk gives the same FP64 state bit for bit (a difference
+    would be a halo or LDS race)."""
+    say("tiling invariance")
+    cfg = solver_config("cloud50", 32)
+    bub = sample_cloud(cloud_spec("cloud50"), MASTER_SEED, 0, 4)
+    outs = [gpu_run(ctx, cfg, "f64", bubbles=bub, n_steps=6, tune=t)[0]
+            for t in [(16, 8, 16, 2), (8, 8, 32, 2), (16, 16, 5, 2), (16, 8, 1, 2)]]
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    again = gpu_run(ctx, cfg, "f64", bubbles=bub, n_steps=6, tune=(16, 8, 16, 2))[0]
+    assert np.array_equal(again, outs[0])
+
+
+@pytest.mark.parametrize("case", ["sod", "water_air"])
+def test_fp64_shock_tube(ctx, case):
+    say("shock tube", case)
+    n = 200
+    cfg = dict(BASE)
+    cfg.update(ndim=1, n=n, eos=dict(EOS))
+    if case == "sod":
+        W = riemann_primitives(1, n, dict(a1r1=0.0, a2r2=1.0, u=0.0, p=1.0, a2=1.0),
+                               dict(a1r1=0.0, a2r2=0.125, u=0.0, p=0.1, a2=1.0))
+    else:
+        W = riemann_primitives(1, n, dict(a1r1=1000.0, a2r2=0.0, u=0.0, p=1e9, a2=0.0),
+                               dict(a1r1=0.0, a2r2=50.0, u=0.0, p=1e5, a2=1.0))
+    U, _, dts = gpu_run(ctx, cfg, "f64", W=W, n_steps=100)
+    R, rdts = OF.run_steps(cfg, OF.prim_to_cons(cfg, W), 100)
+    np.testing.assert_allclose(dts, rdts, rtol=1e-12)
+    assert np.all(max_rel_field(oracle_shape(cfg, U), R) <= 1e-10)
+
+
+def test_fp64_periodic_interface(ctx):
+    say("periodic interface 2d")
+    n = 32
+    cfg = dict(BASE)
+    cfg.update(ndim=2, n=n, eos=dict(EOS), bc="periodic")
+    W = interface_primitives(2, n, seed=11)
+    U, _, _ = gpu_run(ctx, cfg, "f64", W=W, n_steps=40)
+    R, _ = OF.run_steps(cfg, OF.prim_to_cons(cfg, W), 40)
+    assert np.all(max_rel_field(oracle_shape(cfg, U), R) <= 1e-10)
+
+
+# --------------------------------------------------------------------------
+# FP32 stencil, FP64 QoI
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("cloud,n", [("cloud2d", 48), ("cloud500", 32)])
+def test_fp32_cloud_100_steps(ctx, cloud, n):
+    say("fp32 100 steps", cloud, n)
+    cfg = solver_config(cloud, n)
+    bub = sample_cloud(cloud_spec(cloud), MASTER_SEED, 0, 5)
+    U, q, dts = gpu_run(ctx, cfg, "f32", bubbles=bub, n_steps=100)
+    ref = OF.solve(cfg, bub, n_steps=100)
+    R = ref["U"]
+    err = rel_l1(oracle_shape(cfg, U), R)
+    assert np.all(err <= 1e-4), err
+    assert abs(q["p_max"] / ref["p_max"] - 1) <= 5e-3
+    assert q["status"] == 0
+
+
+# --------------------------------------------------------------------------
+# full solves, batching, failure handling
+# --------------------------------------------------------------------------
+
+def test_solve_to_end_time_matches_oracle(ctx):
+    from paper_1705_04374_amd import capi
+    say("solve to t_end 2d 32")
+    cfg = solver_config("cloud2d", 32)
+    bub = sample_cloud(cloud_spec("cloud2d"), MASTER_SEED, 0, 0)
+    T = 2.0e-3
+    q = capi.ofm_solve(ctx, capi.make_spec(cfg, "f64", t_end=T), bub)
+    ref = OF.solve(cfg, bub, t_end=T)
+    assert q["status"] == ref["status"] == 0
+    assert q["steps"] == ref["steps"] and q["t"] == T and ref["t"] == T
+    assert math.isclose(q["p_max"], ref["p_max"], rel_tol=1e-8)
+    assert q["argmax"] == ref["argmax"]
+    assert math.isclose(q["t_at_max"], ref["t_at_max"], rel_tol=1e-10)
+
+
+def test_batch_equals_single_solves(ctx):
+    """Samples of different sizes advanced in the same launches give the same
+    QoI, bit for bit, as when solved alone."""
+    from paper_1705_04374_amd import capi
+    say("batch vs single")
+    T = 6.0e-4
+    specs, bubs = [], []
+    for i, n in enumerate([32, 16, 32, 24, 16]):
+        cfg = solver_config("cloud2d", n)
+        specs.append(capi.make_spec(cfg, "f64", t_end=T))
+        bubs.append(sample_cloud(cloud_spec("cloud2d"), MASTER_SEED, 2, i))
+    qb = capi.ofm_solve_batch(ctx, specs, bubs)
+    for s, b, q in zip(specs, bubs, qb):
+        qs = capi.ofm_solve(ctx, s, b)
+        assert qs == q
+    # and the oracle agrees on one of them
+    ref = OF.solve(solver_config("cloud2d", 24), bubs[3], t_end=T)
+    assert math.isclose(qb[3]["p_max"], ref["p_max"], rel_tol=1e-9) and qb[3]["steps"] == ref["steps"]
+
+
+def test_failure_status_and_step_cap(ctx):
+    import torch
+    from paper_1705_04374_amd import capi
+    say("failure handling")
+    cfg = solver_config("cloud2d", 16)
+    bub = np.array([[0.5, 0.5, 0.0, 0.1]])
+    spec = capi.make_spec(cfg, "f64", n_steps=5)
+    # a NaN planted in the state
+    st, bufs = alloc_state(cfg, "f64")
+    capi.ofm_state_init(ctx, spec, bub, st)
+    torch.cuda.synchronize()
+    bufs[0][3, 37] = float("nan")
+    q, _ = capi.ofm_step(ctx, spec, st, 5)
+    assert q["status"] == capi.SAMPLE_NONFINITE and q["steps"] == 0
+    # negative pressure in pure air: c^2 < 0
+    st, bufs = alloc_state(cfg, "f64")
+    capi.ofm_state_init(ctx, spec, bub, st)
+    torch.cuda.synchronize()
+    c = (8 * 16 + 8)
+    bufs[0][4, c] = -1.0e6     # E below the air's zero-pressure energy
+    q, _ = capi.ofm_step(ctx, spec, st, 5)
+    assert q["status"] == capi.SAMPLE_NEGATIVE_C2
+    # step cap
+    q = capi.ofm_solve(ctx, capi.make_spec(cfg, "f64", t_end=1.0, max_steps=7), bub)
+    assert q["status"] == capi.SAMPLE_MAX_STEPS and q["steps"] == 7
+    # argument errors are call errors, not sample failures
+    bad = capi.make_spec(cfg, "f64", t_end=1.0)
+    bad.n = 3
+    with pytest.raises(capi.OfmError) as e:
+        capi.ofm_solve(ctx, bad, bub)
+    assert e.value.code == capi.OFM_EINVAL

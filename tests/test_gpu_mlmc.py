@@ -1,0 +1,92 @@
+"""GPU parity of the OF-MLMC estimator kernels against the oracle, given
+identical sample QoIs: relative difference <= 1e-12."""
+import numpy as np
+import pytest
+
+import oracle.mlmc as O
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1705_04374_amd import capi
+    c = capi.Context(0)
+    yield c
+    c.close()
+
+
+def toy_terms(L, Ms, seed):
+    rng = np.random.default_rng(seed)
+    terms = []
+    for l in range(L + 1):
+        Y, Z = rng.normal(size=(2, Ms[l]))
+        qf = 3.0 + Y + 0.7 * 2.0 ** -l * Z
+        qc = 3.0 + Y + 0.7 * 2.0 ** -(l - 1) * Z if l else None
+        ok = (rng.uniform(size=Ms[l]) > 0.05).astype(np.int32)
+        terms.append((qf, qc, ok))
+    return terms
+
+
+@pytest.mark.parametrize("L,Ms", [(1, [4000, 300]), (3, [65536, 2000, 100, 7])])
+def test_estimator_matches_oracle(ctx, L, Ms):
+    import torch
+    from paper_1705_04374_amd import capi
+    terms = toy_terms(L, Ms, L)
+    W = np.array([8.0 ** l * (1.0 if l == 0 else 1.125) for l in range(L + 1)])
+    mom = torch.zeros((L + 1, 6), dtype=torch.float64, device="cuda")
+    refs = []
+    for l, (qf, qc, ok) in enumerate(terms):
+        tf = torch.tensor(qf, device="cuda")
+        tc = torch.tensor(qc, device="cuda") if qc is not None else None
+        tok = torch.tensor(ok, device="cuda")
+        capi.ofm_mlmc_moments(ctx, tf, tc, tok, mom[l])
+        refs.append(O.term_moments(qf, qc, ok.astype(bool)))
+    m = mom.cpu().numpy()
+    for l, r in enumerate(refs):
+        got = dict(M=m[l, 0], mean_f=m[l, 1], mean_c=m[l, 2], Vf=m[l, 3], Vc=m[l, 4], C=m[l, 5])
+        for k in ("mean_f", "mean_c", "Vf", "Vc", "C"):
+            assert abs(got[k] - r[k]) <= 1e-12 * max(abs(r[k]), 1e-300), (l, k)
+        assert got["M"] == r["M"]
+    Vf = [r["Vf"] for r in refs]
+    Vc = [r["Vc"] for r in refs]
+    Cv = [r["C"] for r in refs]
+    a_ref = O.coefficients(Vf, Vc, Cv, W)
+    Wd = torch.tensor(W, device="cuda")
+    alpha = torch.zeros(L + 1, dtype=torch.float64, device="cuda")
+    flag = torch.zeros(1, dtype=torch.int32, device="cuda")
+    capi.ofm_ofmlmc_coefficients(ctx, L, mom, Wd, alpha, flag)
+    a = alpha.cpu().numpy()
+    assert flag.item() == 0
+    np.testing.assert_allclose(a, a_ref, rtol=1e-12)
+    sig = torch.zeros(L + 1, dtype=torch.float64, device="cuda")
+    eps2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    capi.ofm_ofmlmc_errors(ctx, L, mom, alpha, sig, eps2)
+    s_ref = O.term_variances(Vf, Vc, Cv, a_ref)
+    np.testing.assert_allclose(sig.cpu().numpy(), s_ref, rtol=1e-12)
+    e_ref = O.error2(s_ref, [r["M"] for r in refs])
+    assert abs(eps2.item() - e_ref) <= 1e-12 * e_ref
+    E = torch.zeros(1, dtype=torch.float64, device="cuda")
+    capi.ofm_ofmlmc_estimate(ctx, L, mom, alpha, E)
+    E_ref = O.estimate([r["mean_f"] for r in refs], [r["mean_c"] for r in refs], a_ref)
+    assert abs(E.item() - E_ref) <= 1e-12 * abs(E_ref)
+    # allocation, both modes
+    have = torch.tensor([r["M"] for r in refs], dtype=torch.int64, device="cuda")
+    out = torch.zeros(L + 1, dtype=torch.int64, device="cuda")
+    for mode, target in ((capi.OFM_MODE_TOLERANCE, 0.003), (capi.OFM_MODE_BUDGET, 1.0e6)):
+        capi.ofm_ofmlmc_optimal_M(ctx, L, sig, Wd, have, mode, target, out, flag)
+        ref = O.optimal_samples(list(s_ref), list(W), [r["M"] for r in refs],
+                                "tol" if mode == capi.OFM_MODE_TOLERANCE else "budget", target)
+        assert out.cpu().tolist() == ref and flag.item() == 0
+
+
+def test_singular_system_falls_back_to_ones(ctx):
+    import torch
+    from paper_1705_04374_amd import capi
+    mom = torch.zeros((3, 6), dtype=torch.float64, device="cuda")
+    mom[:, 0] = 10
+    alpha = torch.zeros(3, dtype=torch.float64, device="cuda")
+    flag = torch.zeros(1, dtype=torch.int32, device="cuda")
+    capi.ofm_ofmlmc_coefficients(ctx, 2, mom, torch.ones(3, dtype=torch.float64, device="cuda"), alpha, flag)
+    assert flag.item() == capi.OFM_ESINGULAR
+    assert alpha.cpu().tolist() == [1.0, 1.0, 1.0]
