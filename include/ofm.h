@@ -71,7 +71,13 @@ typedef struct {
 /* One level-l solve (Sec. 2.2 scheme; Sec. 3.1 initial data).
  * State layout in device memory: structure of arrays, nv = 4 + ndim arrays of
  * n^ndim cells each, variable-major: [v][k][j][i] with i fastest; variables
- * (a1 rho1, a2 rho2, rho u_1..rho u_ndim, E, a2). */
+ * (a1 rho1, a2 rho2, rho u_1..rho u_ndim, Et, a2), where the energy slot holds
+ * Et = E - Pi(a2) = Gamma(a2) p + rho |u|^2 / 2, the total energy of
+ * eq. (system) less the stiffened-gas constant of the mixture
+ * (Pi(a2) = (1-a2) gamma1 pc1/(gamma1-1) + a2 gamma2 pc2/(gamma2-1)).  The
+ * scheme is the same as with E in exact arithmetic; in float this keeps the
+ * pressure of a gas at a few kPa next to water (Pi ~ 4e8 Pa) representable.
+ * ofm_state_to_conserved returns the conserved vector Q with E. */
 typedef struct {
     int32_t ndim;        /* 1, 2 or 3 */
     int32_t n;           /* cells per side, 8 <= n <= 4096 */
@@ -174,11 +180,17 @@ int ofm_sample_cloud(const ofm_cloud_spec* spec, uint64_t seed, uint64_t term, u
 int ofm_state_init(ofm_ctx* ctx, const ofm_solve_spec* spec, const double* bubbles,
                    int32_t n_bubbles, ofm_state_view* st, void* stream);
 
-/* Conserved state in st->u from primitive fields w [dev] of the spec's
- * precision, same layout with variables (a1 rho1, a2 rho2, u_1..u_ndim, p, a2).
+/* State st->u from primitive fields w [dev] of the spec's precision, same
+ * layout with variables (a1 rho1, a2 rho2, u_1..u_ndim, p, a2).
  * Asynchronous. */
 int ofm_state_from_primitive(ofm_ctx* ctx, const ofm_solve_spec* spec, const void* w,
                              ofm_state_view* st, void* stream);
+
+/* Conserved vector Q of eq. (system) of the state st->u, in double:
+ * q [dev] nv x n^ndim, variables (a1 rho1, a2 rho2, rho u, E, a2).
+ * Asynchronous. */
+int ofm_state_to_conserved(ofm_ctx* ctx, const ofm_solve_spec* spec, const ofm_state_view* st, double* q,
+                           void* stream);
 
 /* Advance st->u by n_steps CFL-limited steps (dt = cfl h / max(|u_d| + c),
  * taken at the start of each step, Sec. 2.2) of the three-stage low-storage

@@ -31,12 +31,12 @@
  *   sound speed  frozen mixture value c^2 = ((Gamma+1) p + Pi)/(Gamma rho);
  *   WENO         fifth-order Jiang-Shu, eps = spec->weno_eps (absolute);
  *   positivity   each cell is reconstructed along each axis on its own
- *                (both edge values); the reconstruction is dropped for the
- *                cell's own primitives (first order) when a partial density
- *                would be negative at an edge or at the interior Gauss-Lobatto
- *                point that keeps the cell mean (Zhang-Shu), when a2 would
- *                leave [0, 1] there, or when an edge state has
- *                (Gamma+1) p + Pi <= 0;
+ *                (both edge values); a partial density that would be negative
+ *                at an edge or at the interior Gauss-Lobatto point that keeps
+ *                the cell mean (Zhang-Shu), or an a2 that would leave [0, 1]
+ *                there, takes the cell value at both edges (first order for
+ *                that variable); if an edge state then has (Gamma+1) p + Pi
+ *                <= 0 the whole cell is first order;
  *   HLLC         Davis wave-speed estimates; the tie S* = 0 takes the left
  *                star state; the a2 flux is a2_K u_f with the face velocity
  *                u_f of the HLLC flux of a passive scalar;
@@ -278,16 +278,20 @@ void orc_hllc(const orc_spec* s, int dir, const double* wl, const double* wr, do
 
 /* Edge values of the centre cell c of the primitive stencil a, b, c, d, e
  * (cells c-2 .. c+2 along one axis): left edge into wminus, right edge into
- * wplus (either may be NULL).  The reconstruction of the cell is kept only if
- *   - both edge values of a1r1 and a2r2 are >= 0 and so is the interior value
- *     (12 mean - left - right)/10 of the four-point Gauss-Lobatto rule that
- *     reproduces the cell mean (Zhang-Shu positivity condition), up to
- *     round-off (ORC_ROUND_TOL of the largest mixture density in the stencil);
- *   - both edge values and the interior value of a2 lie in [0, 1], up to
- *     ORC_ROUND_TOL;
- *   - both edge states have (Gamma+1) p + Pi > 0 (positive c^2);
- * otherwise both edges take the cell's own primitives (first order).
- * Returns 1 when the fallback was taken. */
+ * wplus (either may be NULL).
+ *   - each partial density keeps its reconstruction only if it is >= 0 at
+ *     both edges and at the interior value (12 mean - left - right)/10 of the
+ *     four-point Gauss-Lobatto rule that reproduces the cell mean (Zhang-Shu
+ *     positivity condition), up to round-off (ORC_ROUND_TOL of the largest
+ *     mixture density in the stencil); otherwise both its edges take the
+ *     cell value;
+ *   - a2 likewise keeps its reconstruction only if it lies in [0, 1] at the
+ *     same three points, up to ORC_ROUND_TOL;
+ *   - if an edge state then has (Gamma+1) p + Pi <= 0 (no positive c^2), all
+ *     variables take the cell values (first order).
+ * Replacing only the variable that fails keeps a decision taken on round-off
+ * from moving the other edge values.  Returns 1 when any replacement was
+ * made. */
 int orc_cell_edges(const orc_spec* s, const double* a, const double* b, const double* c,
                    const double* d, const double* e, double eps, double* wminus, double* wplus)
 {
@@ -298,7 +302,6 @@ int orc_cell_edges(const orc_spec* s, const double* a, const double* b, const do
         lp[v] = orc_weno5_right_edge(a[v], b[v], c[v], d[v], e[v], eps);
         lm[v] = orc_weno5_right_edge(e[v], d[v], c[v], b[v], a[v], eps);
     }
-    int ok = 1;
     /* round-off below the mixture density of the stencil does not count as
      * negative (a partial density is part of the mixture density) */
     double big = 0.0;
@@ -307,19 +310,25 @@ int orc_cell_edges(const orc_spec* s, const double* a, const double* b, const do
         for (int k = 0; k < 5; ++k) big = fmax(big, fabs(st5[k][0] + st5[k][1]));
     }
     double tol = -ORC_ROUND_TOL * big;
+    int keep[8];
+    for (int v = 0; v < nv; ++v) keep[v] = 1;
+    /* each partial density on its own */
     for (int v = 0; v < 2; ++v) {
         double mid = (12.0 * c[v] - lm[v] - lp[v]) / 10.0;
-        if (!(lm[v] >= tol) || !(lp[v] >= tol) || !(mid >= tol)) ok = 0;
+        if (!(lm[v] >= tol) || !(lp[v] >= tol) || !(mid >= tol)) keep[v] = 0;
     }
+    /* the volume fraction */
     {
         int v = 3 + nd;
         double lo = -ORC_ROUND_TOL, hi = 1.0 + ORC_ROUND_TOL;
         double mid = (12.0 * c[v] - lm[v] - lp[v]) / 10.0;
-        if (!(lm[v] >= lo && lm[v] <= hi)) ok = 0;
-        if (!(lp[v] >= lo && lp[v] <= hi)) ok = 0;
-        if (!(mid >= lo && mid <= hi)) ok = 0;
+        if (!(lm[v] >= lo && lm[v] <= hi) || !(lp[v] >= lo && lp[v] <= hi) || !(mid >= lo && mid <= hi)) keep[v] = 0;
     }
-    if (ok) {
+    for (int v = 0; v < nv; ++v)
+        if (!keep[v]) { lm[v] = c[v]; lp[v] = c[v]; }
+    /* positive c^2 at both edges, else the whole cell is first order */
+    int ok = 1;
+    {
         const double* sides[2] = { lm, lp };
         for (int k = 0; k < 2; ++k) {
             double a2 = sides[k][3 + nd];
@@ -331,7 +340,9 @@ int orc_cell_edges(const orc_spec* s, const double* a, const double* b, const do
         if (wminus) wminus[v] = ok ? lm[v] : c[v];
         if (wplus) wplus[v] = ok ? lp[v] : c[v];
     }
-    return !ok;
+    int nfb = 0;
+    for (int v = 0; v < nv; ++v) nfb += !keep[v];
+    return (nfb > 0) || !ok;
 }
 
 /* ------------------------------------------------------------------ */

@@ -25,7 +25,7 @@ SAMPLE_OK, SAMPLE_NONFINITE, SAMPLE_NEGATIVE_C2, SAMPLE_MAX_STEPS = 0, 1, 2, 3
 # Every symbol include/ofm.h declares.
 EXPORTS = [
     "ofm_ctx_create", "ofm_ctx_destroy", "ofm_last_error", "ofm_sample_cloud", "ofm_state_init",
-    "ofm_state_from_primitive", "ofm_step", "ofm_solve", "ofm_solve_batch", "ofm_last_solve_stats",
+    "ofm_state_from_primitive", "ofm_state_to_conserved", "ofm_step", "ofm_solve", "ofm_solve_batch", "ofm_last_solve_stats",
     "ofm_mlmc_moments", "ofm_ofmlmc_coefficients", "ofm_ofmlmc_errors", "ofm_ofmlmc_estimate",
     "ofm_ofmlmc_optimal_M", "ofm_tune_set", "ofm_kernel_timing", "ofm_kernel_times",
 ]
@@ -105,6 +105,7 @@ def lib():
         L.ofm_sample_cloud.argtypes = [C.POINTER(CloudSpec), C.c_uint64, C.c_uint64, C.c_uint64, dp]
         L.ofm_state_init.argtypes = [vp, C.POINTER(SolveSpec), dp, i32, C.POINTER(StateView), vp]
         L.ofm_state_from_primitive.argtypes = [vp, C.POINTER(SolveSpec), vp, C.POINTER(StateView), vp]
+        L.ofm_state_to_conserved.argtypes = [vp, C.POINTER(SolveSpec), C.POINTER(StateView), vp, vp]
         L.ofm_step.argtypes = [vp, C.POINTER(SolveSpec), C.POINTER(StateView), i64, C.POINTER(Qoi), dp, vp]
         L.ofm_solve.argtypes = [vp, C.POINTER(SolveSpec), dp, i32, C.POINTER(Qoi), vp]
         L.ofm_solve_batch.argtypes = [vp, C.POINTER(BatchItem), i32, C.POINTER(Qoi), vp]
@@ -234,6 +235,10 @@ def ofm_state_init(ctx: Context, spec: SolveSpec, bubbles, st: StateView, stream
 
 def ofm_state_from_primitive(ctx: Context, spec: SolveSpec, w, st: StateView, stream=None):
     ctx.check(lib().ofm_state_from_primitive(ctx.h, C.byref(spec), _dptr(w), C.byref(st), _stream(stream)))
+
+
+def ofm_state_to_conserved(ctx: Context, spec: SolveSpec, st: StateView, q, stream=None):
+    ctx.check(lib().ofm_state_to_conserved(ctx.h, C.byref(spec), C.byref(st), _dptr(q), _stream(stream)))
 
 
 def ofm_step(ctx: Context, spec: SolveSpec, st: StateView, n_steps: int, stream=None):

@@ -448,6 +448,19 @@ int ofm_state_from_primitive(ofm_ctx* ctx, const ofm_solve_spec* spec, const voi
     return OFM_OK;
 }
 
+int ofm_state_to_conserved(ofm_ctx* ctx, const ofm_solve_spec* spec, const ofm_state_view* st, double* q,
+                           void* stream)
+{
+    if (!ctx) return fail(nullptr, OFM_EINVAL, "null context");
+    int rc = validate(ctx, spec);
+    if (rc) return rc;
+    if (!q || !st || !st->u) return fail(ctx, OFM_EINVAL, "ofm_state_to_conserved: null pointer");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, launch_to_conserved(spec->precision, spec->ndim, make_phys(*spec), st->u, q, cells_of(*spec),
+                                    (hipStream_t)stream));
+    return OFM_OK;
+}
+
 int ofm_step(ofm_ctx* ctx, const ofm_solve_spec* spec, ofm_state_view* st, int64_t n_steps, ofm_qoi* qoi,
              double* dts, void* stream)
 {

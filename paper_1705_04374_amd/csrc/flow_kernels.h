@@ -22,6 +22,8 @@ hipError_t launch_reduce(int precision, int ndim, int tx, int ty, const LaunchAr
 hipError_t launch_finalize(const SampleDesc* desc, SampleState* state, const TilePartial* part, int n_samples,
                            int initial, double* dt_log, int64_t dt_log_len, hipStream_t s);
 hipError_t launch_init(int precision, int ndim, const InitLaunch& L, hipStream_t s);
+hipError_t launch_to_conserved(int precision, int ndim, const PhysD& ph, const void* u, double* q, int64_t ncell,
+                               hipStream_t s);
 hipError_t launch_prim_to_cons(int precision, int ndim, const PhysD& ph, const void* w, void* u, int64_t ncell,
                                hipStream_t s);
 

@@ -21,6 +21,15 @@
 // Layout in HBM: structure of arrays, one contiguous array per variable,
 // x fastest; three arrays per sample (two ping-pong state buffers and the
 // low-storage register dU).
+//
+// Energy variable: the state carries Et = E - Pi(a2) = Gamma(a2) p + rho|u|^2/2
+// in place of the total energy E.  Since Pi(a2) = Pi_1 + a2 (Pi_2 - Pi_1) is
+// linear in a2, the HLLC energy flux splits exactly into the flux of Et plus
+// Pi(a2_K) u_f, and the update of Et is the one of E minus (Pi_2 - Pi_1) times
+// the one of a2:  L(Et) = -sum_d dF(Et)/h - Pi(a2 + K) sum_d du_f/h.  This is
+// the same scheme in exact arithmetic; in float it avoids recovering a
+// pressure of a few kPa from E ~ 4e8 Pa (water's Pi), which would cost most
+// of the significand.
 #include "flow_kernels.h"
 
 #include <math.h>
@@ -61,7 +70,7 @@ __device__ __forceinline__ int bc_map(int i, int n, int bc)
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
-// Conserved -> primitive (a1r1, a2r2, u_1..u_d, p, a2).
+// State -> primitive (a1r1, a2r2, u_1..u_d, p, a2); the energy slot holds Et.
 template <typename T, int ND>
 __device__ __forceinline__ void to_prim(const Phys<T>& ph, const T* q, T* w)
 {
@@ -76,7 +85,7 @@ __device__ __forceinline__ void to_prim(const Phys<T>& ph, const T* q, T* w)
         ke += q[2 + m] * w[2 + m];
     }
     T a2 = q[3 + ND];
-    w[2 + ND] = (q[2 + ND] - T(0.5) * ke - ph.pinf(a2)) * Num<T>::rcp(ph.gamma(a2));
+    w[2 + ND] = (q[2 + ND] - T(0.5) * ke) * Num<T>::rcp(ph.gamma(a2));
     w[3 + ND] = a2;
 }
 
@@ -116,13 +125,15 @@ __device__ __forceinline__ void weno5_cell(T a, T b, T c, T d, T e, T eps, T& lo
     lo = (w0 * p0 + w1 * p1 + w2 * p2) * Num<T>::rcp(w0 + w1 + w2);
 }
 
-// Edges of one cell along one axis with the positivity / bounds check: the
-// reconstruction is kept only if the partial densities stay >= 0 at both
-// edges and at the interior Gauss-Lobatto point (12 mean - lo - hi)/10, a2
-// stays in [0, 1] there, and both edge states have (Gamma+1) p + Pi > 0
-// (each up to round-off: round_tol times the stencil's mixture density for
-// the partial densities, round_tol for a2); otherwise both edges take the
-// cell's primitives.
+// Edges of one cell along one axis with the positivity / bounds checks.
+// Each partial density keeps its reconstruction only if it stays >= 0 at both
+// edges and at the interior Gauss-Lobatto point (12 mean - lo - hi)/10 that
+// keeps the cell mean (up to round_tol times the stencil's mixture density);
+// a2 keeps its reconstruction only if it stays in [0, 1] at the same three
+// points (up to round_tol).  A variable that fails takes the cell value at
+// both edges (first order for that variable alone, so that a decision taken
+// on round-off moves the edges by round-off).  If then either edge state has
+// (Gamma+1) p + Pi <= 0, the whole cell is first order.
 template <typename T, int ND>
 __device__ __forceinline__ void cell_edges(const Phys<T>& ph, const T (&s)[5][4 + ND],
                                            T (&lo)[4 + ND], T (&hi)[4 + ND])
@@ -130,28 +141,28 @@ __device__ __forceinline__ void cell_edges(const Phys<T>& ph, const T (&s)[5][4 
     constexpr int NV = 4 + ND;
 #pragma unroll
     for (int v = 0; v < NV; ++v) weno5_cell<T>(s[0][v], s[1][v], s[2][v], s[3][v], s[4][v], ph.eps, lo[v], hi[v]);
-    bool ok = true;
-    // round-off below the stencil's mixture density does not count as
-    // negative (a partial density is part of the mixture density)
     T big = T(0);
 #pragma unroll
     for (int k = 0; k < 5; ++k) big = fmax(big, fabs(s[k][0] + s[k][1]));
     const T tol = -Num<T>::round_tol * big;
 #pragma unroll
     for (int v = 0; v < 2; ++v) {
-        T mid = (T(12) * s[2][v] - lo[v] - hi[v]) * T(0.1);
-        ok = ok && (lo[v] >= tol) && (hi[v] >= tol) && (mid >= tol);
+        const T mid = (T(12) * s[2][v] - lo[v] - hi[v]) * T(0.1);
+        const bool keep = (lo[v] >= tol) && (hi[v] >= tol) && (mid >= tol);
+        lo[v] = keep ? lo[v] : s[2][v];
+        hi[v] = keep ? hi[v] : s[2][v];
     }
     {
         constexpr int v = 3 + ND;
         const T lb = -Num<T>::round_tol, ub = T(1) + Num<T>::round_tol;
-        T mid = (T(12) * s[2][v] - lo[v] - hi[v]) * T(0.1);
-        ok = ok && (lo[v] >= lb) && (lo[v] <= ub) && (hi[v] >= lb) && (hi[v] <= ub) && (mid >= lb) && (mid <= ub);
+        const T mid = (T(12) * s[2][v] - lo[v] - hi[v]) * T(0.1);
+        const bool keep = (lo[v] >= lb) && (lo[v] <= ub) && (hi[v] >= lb) && (hi[v] <= ub) && (mid >= lb) && (mid <= ub);
+        lo[v] = keep ? lo[v] : s[2][v];
+        hi[v] = keep ? hi[v] : s[2][v];
     }
-    T cl = (ph.gamma(lo[3 + ND]) + T(1)) * lo[2 + ND] + ph.pinf(lo[3 + ND]);
-    T ch = (ph.gamma(hi[3 + ND]) + T(1)) * hi[2 + ND] + ph.pinf(hi[3 + ND]);
-    ok = ok && (cl > T(0)) && (ch > T(0));
-    if (!ok) {
+    const T cl = (ph.gamma(lo[3 + ND]) + T(1)) * lo[2 + ND] + ph.pinf(lo[3 + ND]);
+    const T ch = (ph.gamma(hi[3 + ND]) + T(1)) * hi[2 + ND] + ph.pinf(hi[3 + ND]);
+    if (!((cl > T(0)) && (ch > T(0)))) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) { lo[v] = s[2][v]; hi[v] = s[2][v]; }
     }
@@ -160,7 +171,8 @@ __device__ __forceinline__ void cell_edges(const Phys<T>& ph, const T (&s)[5][4 
 // HLLC flux along axis DIR (Toro 1994) with Davis wave speeds; the a2 flux
 // is a2_K u_f where u_f is the face velocity of the HLLC flux of a passive
 // scalar (Johnsen-Colonius adaptation).  f[0..NV-2]: fluxes of (a1r1, a2r2,
-// momenta, E); f[NV-1]: a2 flux; f[NV]: u_f.
+// momenta, Et); f[NV-1]: a2 flux; f[NV]: u_f.  The flux of E is
+// f[NV-2] + Pi(a2_K) u_f.
 template <typename T, int ND, int DIR>
 __device__ __forceinline__ void hllc(const Phys<T>& ph, const T (&wl)[4 + ND], const T (&wr)[4 + ND],
                                      T (&f)[5 + ND])
@@ -174,8 +186,9 @@ __device__ __forceinline__ void hllc(const Phys<T>& ph, const T (&wl)[4 + ND], c
     T kel = T(0), ker = T(0);
 #pragma unroll
     for (int m = 0; m < ND; ++m) { kel += wl[2 + m] * wl[2 + m]; ker += wr[2 + m] * wr[2 + m]; }
-    T El = gl * pl + Pl + T(0.5) * rl * kel;
-    T Er = gr * pr + Pr + T(0.5) * rr * ker;
+    // energies without Pi (its flux Pi(a2_K) u_f is added by the caller's source)
+    T El = gl * pl + T(0.5) * rl * kel;
+    T Er = gr * pr + T(0.5) * rr * ker;
     T cl = Num<T>::sqrt_(((gl + T(1)) * pl + Pl) * Num<T>::rcp(gl * rl));
     T cr = Num<T>::sqrt_(((gr + T(1)) * pr + Pr) * Num<T>::rcp(gr * rr));
     T sl = fmin(ul - cl, ur - cr);
@@ -270,7 +283,7 @@ __device__ __forceinline__ void reduce_cell(const PhysD& ph, const T (&q)[4 + ND
     double a2 = qd[3 + ND];
     double G = ph.g1inv + a2 * (ph.g2inv - ph.g1inv);
     double P = ph.pi1 + a2 * (ph.pi2 - ph.pi1);
-    double p = (qd[2 + ND] - 0.5 * ke - P) / G;
+    double p = (qd[2 + ND] - 0.5 * ke) / G;
     finite = finite && isfinite(p);
     if (!finite) { r.n_nf++; return; }
     double c2 = ((G + 1.0) * p + P) / (G * rho);
@@ -471,7 +484,10 @@ stage_kernel(LaunchArgs a, int stage)
         T L[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) L[v] = sum[v] * ih;
-        L[NV - 1] += (wc[3 + ND] + k_coef<T>(ph, wc[3 + ND], wc[2 + ND])) * (sum[NV] * ih);
+        const T sk = wc[3 + ND] + k_coef<T>(ph, wc[3 + ND], wc[2 + ND]);
+        const T divu = sum[NV] * ih;
+        L[NV - 1] += sk * divu;              // R_7 = (a2 + K) div u
+        L[NV - 2] -= ph.pinf(sk) * divu;     // Et = E - Pi(a2): -Pi(a2 + K) div u
         T qn[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -764,7 +780,6 @@ __global__ void __launch_bounds__(256) init_kernel(InitArgs a)
     s = s < 0.0 ? 0.0 : (s > 1.0 ? 1.0 : s);
     const double p = a.p_bubble + (a.p_inf - a.p_bubble) * (s * s * (3.0 - 2.0 * s));
     const double G = a.ph.g1inv + a2 * (a.ph.g2inv - a.ph.g1inv);
-    const double P = a.ph.pi1 + a2 * (a.ph.pi2 - a.ph.pi1);
     const int64_t ncell = ND == 3 ? (int64_t)n * n * n : (ND == 2 ? (int64_t)n * n : (int64_t)n);
     const int64_t idx = ((int64_t)k * (ND >= 2 ? n : 1) + j) * n + i;
     T* u = (T*)a.u;
@@ -773,7 +788,7 @@ __global__ void __launch_bounds__(256) init_kernel(InitArgs a)
     u[1 * ncell + idx] = (T)(a2 * a.rho2);
 #pragma unroll
     for (int mm = 0; mm < ND; ++mm) u[(2 + mm) * ncell + idx] = (T)0;
-    u[(2 + ND) * ncell + idx] = (T)(G * p + P);
+    u[(2 + ND) * ncell + idx] = (T)(G * p);   // Et at rest
     u[(NV - 1) * ncell + idx] = (T)a2;
 }
 
@@ -798,8 +813,22 @@ __global__ void __launch_bounds__(256) prim_to_cons_kernel(PhysD phd, const T* w
         ke += rho * wv[2 + m] * wv[2 + m];
     }
     const T a2 = wv[3 + ND];
-    u[(2 + ND) * ncell + c] = ph.gamma(a2) * wv[2 + ND] + ph.pinf(a2) + T(0.5) * ke;
+    u[(2 + ND) * ncell + c] = ph.gamma(a2) * wv[2 + ND] + T(0.5) * ke;
     u[(3 + ND) * ncell + c] = a2;
+}
+
+// Library state -> the conserved vector Q of eq. (system) in double
+// (E = Et + Pi(a2)), element-wise.
+template <typename T, int ND>
+__global__ void __launch_bounds__(256) to_conserved_kernel(PhysD ph, const T* u, double* q, int64_t ncell)
+{
+    constexpr int NV = 4 + ND;
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= ncell) return;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) q[v * ncell + c] = (double)u[v * ncell + c];
+    const double a2 = (double)u[(NV - 1) * ncell + c];
+    q[(NV - 2) * ncell + c] += ph.pi1 + a2 * (ph.pi2 - ph.pi1);
 }
 
 // ---------------------------------------------------------------------------
@@ -898,6 +927,24 @@ hipError_t launch_prim_to_cons(int precision, int ndim, const PhysD& ph, const v
         if (ndim == 3) PL(float, 3); else if (ndim == 2) PL(float, 2); else PL(float, 1);
     }
 #undef PL
+    return hipGetLastError();
+}
+
+}  // namespace ofm
+
+namespace ofm {
+
+hipError_t launch_to_conserved(int precision, int ndim, const PhysD& ph, const void* u, double* q, int64_t ncell,
+                               hipStream_t s)
+{
+    const int blocks = (int)((ncell + 255) / 256);
+#define CL(T, ND) hipLaunchKernelGGL((to_conserved_kernel<T, ND>), dim3(blocks), dim3(256), 0, s, ph, (const T*)u, q, ncell)
+    if (precision == OFM_F64) {
+        if (ndim == 3) CL(double, 3); else if (ndim == 2) CL(double, 2); else CL(double, 1);
+    } else {
+        if (ndim == 3) CL(float, 3); else if (ndim == 2) CL(float, 2); else CL(float, 1);
+    }
+#undef CL
     return hipGetLastError();
 }
 

@@ -19,14 +19,16 @@ def alloc_state(cfg: dict, precision: str):
     return _alloc(cfg, precision)
 
 
-def read_state(st, bufs) -> np.ndarray:
-    """Current state (st.u) as float64 numpy [nv, cells]."""
+def read_state(ctx, spec, st) -> np.ndarray:
+    """Conserved vector Q of eq. (system) of the current state, as float64
+    numpy [nv, cells] (the library's to-conserved kernel adds Pi(a2) back to
+    its energy slot)."""
     import torch
+    from paper_1705_04374_amd import capi
+    q = torch.empty((4 + spec.ndim, spec.n ** spec.ndim), dtype=torch.float64, device="cuda")
+    capi.ofm_state_to_conserved(ctx, spec, st, q)
     torch.cuda.synchronize()
-    for b in bufs:
-        if b.data_ptr() == st.u:
-            return b.double().cpu().numpy()
-    raise AssertionError("state pointer not among the buffers")
+    return q.cpu().numpy()
 
 
 def oracle_shape(cfg: dict, a: np.ndarray) -> np.ndarray:

@@ -52,7 +52,7 @@ def gpu_run(ctx, cfg, precision, bubbles=None, W=None, n_steps=0, tune=None):
     q, dts = (None, np.zeros(0))
     if n_steps:
         q, dts = capi.ofm_step(ctx, spec, st, n_steps)
-    return read_state(st, bufs), q, dts
+    return read_state(ctx, spec, st), q, dts
 
 
 # --------------------------------------------------------------------------
