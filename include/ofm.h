@@ -87,7 +87,8 @@ typedef struct {
     int32_t reserved;
     double cfl;          /* Courant number (0.3 in the paper, Sec. 3.1) */
     ofm_eos eos;
-    double rho1, rho2;   /* initial phase densities */
+    double rho1, rho2;   /* initial phase densities (also the scale below which a
+                            negative partial density counts as round-off) */
     double p_bubble;     /* pressure inside the cloud */
     double p_inf;        /* ambient pressure */
     double center[3];    /* cloud centre */
@@ -137,7 +138,7 @@ typedef struct {
 } ofm_state_view;
 
 /* One member of a batched solve.  Items of one call share ndim, precision,
- * bc, eos and weno_eps; n, t_end and the cloud may differ.  A coupled
+ * bc, eos, rho1, rho2 and weno_eps; n, t_end and the cloud may differ.  A coupled
  * fine/coarse pair is two items with the same bubbles (Sec. 2.4.1). */
 typedef struct {
     const ofm_solve_spec* spec;

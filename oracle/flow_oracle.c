@@ -282,9 +282,10 @@ void orc_hllc(const orc_spec* s, int dir, const double* wl, const double* wr, do
  *   - each partial density keeps its reconstruction only if it is >= 0 at
  *     both edges and at the interior value (12 mean - left - right)/10 of the
  *     four-point Gauss-Lobatto rule that reproduces the cell mean (Zhang-Shu
- *     positivity condition), up to round-off (ORC_ROUND_TOL of the largest
- *     mixture density in the stencil); otherwise both its edges take the
- *     cell value;
+ *     positivity condition), up to round-off: ORC_ROUND_TOL times the
+ *     phase's reference density (the initial rho_k) or the largest magnitude
+ *     of that partial density in the stencil, whichever is larger; otherwise
+ *     both its edges take the cell value;
  *   - a2 likewise keeps its reconstruction only if it lies in [0, 1] at the
  *     same three points, up to ORC_ROUND_TOL;
  *   - if an edge state then has (Gamma+1) p + Pi <= 0 (no positive c^2), all
@@ -302,18 +303,15 @@ int orc_cell_edges(const orc_spec* s, const double* a, const double* b, const do
         lp[v] = orc_weno5_right_edge(a[v], b[v], c[v], d[v], e[v], eps);
         lm[v] = orc_weno5_right_edge(e[v], d[v], c[v], b[v], a[v], eps);
     }
-    /* round-off below the mixture density of the stencil does not count as
-     * negative (a partial density is part of the mixture density) */
-    double big = 0.0;
-    {
-        const double* st5[5] = { a, b, c, d, e };
-        for (int k = 0; k < 5; ++k) big = fmax(big, fabs(st5[k][0] + st5[k][1]));
-    }
-    double tol = -ORC_ROUND_TOL * big;
     int keep[8];
     for (int v = 0; v < nv; ++v) keep[v] = 1;
-    /* each partial density on its own */
+    /* each partial density on its own; round-off below the phase's scale
+     * (its reference density, or the largest value in the stencil if that is
+     * larger) does not count as negative */
     for (int v = 0; v < 2; ++v) {
+        double big = v == 0 ? s->rho1 : s->rho2;
+        big = fmax(big, fmax(fmax(fabs(a[v]), fabs(b[v])), fmax(fmax(fabs(c[v]), fabs(d[v])), fabs(e[v]))));
+        double tol = -ORC_ROUND_TOL * big;
         double mid = (12.0 * c[v] - lm[v] - lp[v]) / 10.0;
         if (!(lm[v] >= tol) || !(lp[v] >= tol) || !(mid >= tol)) keep[v] = 0;
     }

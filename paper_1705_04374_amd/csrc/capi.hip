@@ -82,6 +82,8 @@ static PhysD make_phys(const ofm_solve_spec& s)
     p.gamma2 = s.eos.gamma2;
     p.pc2 = s.eos.pc2;
     p.eps = s.weno_eps;
+    p.rho1 = s.rho1;
+    p.rho2 = s.rho2;
     return p;
 }
 
@@ -145,8 +147,8 @@ static int run(ofm_ctx* ctx, std::vector<Member>& mem, bool init, double* dts_ho
     const int prec = s0.precision, nd = s0.ndim, bc = s0.bc;
     for (const Member& m : mem) {
         if (m.spec.ndim != nd || m.spec.precision != prec || m.spec.bc != bc || m.spec.weno_eps != s0.weno_eps ||
-            memcmp(&m.spec.eos, &s0.eos, sizeof(ofm_eos)) != 0)
-            return fail(ctx, OFM_EINVAL, "batched items must share ndim, precision, bc, eos and weno_eps");
+            m.spec.rho1 != s0.rho1 || m.spec.rho2 != s0.rho2 || memcmp(&m.spec.eos, &s0.eos, sizeof(ofm_eos)) != 0)
+            return fail(ctx, OFM_EINVAL, "batched items must share ndim, precision, bc, eos, rho1, rho2 and weno_eps");
         if (bc == OFM_BC_PERIODIC && m.spec.n < 6) return fail(ctx, OFM_EINVAL, "periodic grids need n >= 6");
     }
     // tiling

@@ -55,9 +55,11 @@ template <> struct Num<double> {
 template <typename T> struct Phys {
     T g1inv, dginv, pi1, dpi, eps;
     T gam1, pc1, gam2, pc2;
+    T rho1, rho2;      // reference phase densities (scale of the positivity checks)
     __device__ __forceinline__ explicit Phys(const PhysD& d)
         : g1inv((T)d.g1inv), dginv((T)(d.g2inv - d.g1inv)), pi1((T)d.pi1), dpi((T)(d.pi2 - d.pi1)),
-          eps((T)d.eps), gam1((T)d.gamma1), pc1((T)d.pc1), gam2((T)d.gamma2), pc2((T)d.pc2) {}
+          eps((T)d.eps), gam1((T)d.gamma1), pc1((T)d.pc1), gam2((T)d.gamma2), pc2((T)d.pc2),
+          rho1((T)d.rho1), rho2((T)d.rho2) {}
     // mixture stiffened-gas coefficients under isobaric closure:
     // p = (E - rho|u|^2/2 - Pi(a2)) / Gamma(a2)
     __device__ __forceinline__ T gamma(T a2) const { return g1inv + a2 * dginv; }
@@ -128,7 +130,8 @@ __device__ __forceinline__ void weno5_cell(T a, T b, T c, T d, T e, T eps, T& lo
 // Edges of one cell along one axis with the positivity / bounds checks.
 // Each partial density keeps its reconstruction only if it stays >= 0 at both
 // edges and at the interior Gauss-Lobatto point (12 mean - lo - hi)/10 that
-// keeps the cell mean (up to round_tol times the stencil's mixture density);
+// keeps the cell mean (up to round_tol times the phase's reference density
+// or the largest magnitude of that partial density in the stencil);
 // a2 keeps its reconstruction only if it stays in [0, 1] at the same three
 // points (up to round_tol).  A variable that fails takes the cell value at
 // both edges (first order for that variable alone, so that a decision taken
@@ -141,12 +144,12 @@ __device__ __forceinline__ void cell_edges(const Phys<T>& ph, const T (&s)[5][4 
     constexpr int NV = 4 + ND;
 #pragma unroll
     for (int v = 0; v < NV; ++v) weno5_cell<T>(s[0][v], s[1][v], s[2][v], s[3][v], s[4][v], ph.eps, lo[v], hi[v]);
-    T big = T(0);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) big = fmax(big, fabs(s[k][0] + s[k][1]));
-    const T tol = -Num<T>::round_tol * big;
 #pragma unroll
     for (int v = 0; v < 2; ++v) {
+        T big = v == 0 ? ph.rho1 : ph.rho2;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) big = fmax(big, fabs(s[k][v]));
+        const T tol = -Num<T>::round_tol * big;
         const T mid = (T(12) * s[2][v] - lo[v] - hi[v]) * T(0.1);
         const bool keep = (lo[v] >= tol) && (hi[v] >= tol) && (mid >= tol);
         lo[v] = keep ? lo[v] : s[2][v];

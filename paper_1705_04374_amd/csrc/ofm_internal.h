@@ -16,6 +16,7 @@ struct PhysD {
     double pi2;        // gamma2 pc2 / (gamma2 - 1)
     double gamma1, pc1, gamma2, pc2;
     double eps;        // WENO epsilon
+    double rho1, rho2; // reference phase densities
 };
 
 // Static description of one sample in a launch.
