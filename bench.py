@@ -19,8 +19,8 @@ The JSON line also carries
                the per-launch algorithmic flops (vector ALU roofline); `bound`
                names the roofline the kernel is closer to;
   cpu_baseline the serial FP64 oracle timed on this host's cores on a bounded
-               sample of the same workload (one 48^3 box of the 256^3 cloud per
-               process, 2 steps each);
+               sample of the same workload (one 64^3 box of the 256^3 cloud per
+               process, 4 steps each);
   fp64         the same measurement with the stencil in double.
 """
 from __future__ import annotations
@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 side measurement")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy three times (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -84,15 +86,16 @@ def measure(ctx, capi, cfg, bub, precision, steps, warmup):
     return dict(wall=wall, q=q, kt=kt)
 
 
-def cpu_baseline(cfg, bub, seconds_hint=20.0):
-    """Serial FP64 oracle on P host cores, each advancing its own 48^3 box of
-    the same 256^3 cloud by 2 steps (the box interior is exact; rate counts
-    every box cell)."""
+def cpu_baseline(cfg, bub):
+    """Serial FP64 oracle on P host cores, each advancing its own 64^3 box of
+    the same 256^3 cloud by 4 steps (the rate counts every box cell; cells
+    near the box sides see box ghosts, the arithmetic per cell is the same)."""
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
     P = min(os.cpu_count() or 1, 16)
     n = cfg["n"]
-    b = 48
+    b = 64
+    nst = 4
     rng_boxes = []
     for k in range(P):
         o = (n // 2 - b) + (k * 37) % max(1, n // 2)
@@ -103,25 +106,25 @@ def cpu_baseline(cfg, bub, seconds_hint=20.0):
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ProcessPoolExecutor(max_workers=P, mp_context=ctx) as ex:
-        res = list(ex.map(_cpu_box, [(cfg, bub, lo, b, dt) for lo in rng_boxes]))
+        res = list(ex.map(_cpu_box, [(cfg, bub, lo, b, dt, nst) for lo in rng_boxes]))
     wall = time.perf_counter() - t0
     cells = sum(r[0] for r in res)
     step_s = max(r[1] for r in res)
     return dict(value=cells / step_s, unit="cell-updates/s", cores=P, kind="oracle",
-                sample="%d processes x one %d^3 box of the %d^3 500-bubble cloud, 2 FP64 steps each "
-                       "(init excluded), wall %.1f s" % (P, b, n, wall))
+                sample="%d processes x one %d^3 box of the %d^3 500-bubble cloud, %d FP64 steps each "
+                       "(init excluded), wall %.1f s" % (P, b, n, nst, wall))
 
 
 def _cpu_box(args):
-    cfg, bub, lo, b, dt = args
+    cfg, bub, lo, b, dt, nst = args
     import oracle.flow as OF
     box = (lo, (b, b, b))
     t0 = time.perf_counter()
     OF.box_steps(cfg, bub, box, [])
     t1 = time.perf_counter()
-    OF.box_steps(cfg, bub, box, [dt, dt])
+    OF.box_steps(cfg, bub, box, [dt] * nst)
     t2 = time.perf_counter()
-    return (2 * b ** 3, (t2 - t1) - (t1 - t0))
+    return (nst * b ** 3, (t2 - t1) - (t1 - t0))
 
 
 def main():
@@ -135,6 +138,15 @@ def main():
     from paper_1705_04374_amd import capi
     from workloads.configs import MASTER_SEED, cloud_spec, solver_config
 
+    if a.calibrate_copy:
+        # a plain copy of known size: 2^28 floats read and 2^28 written per launch
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+        torch.cuda.empty_cache()
     n = a.n
     cfg = solver_config("cloud500", n)
     bub = capi.ofm_sample_cloud(cloud_spec("cloud500"), MASTER_SEED, 0, 0)
