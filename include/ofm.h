@@ -282,6 +282,57 @@ int ofm_ofmlmc_optimal_M(ofm_ctx* ctx, int32_t L, const double* sig_t2, const do
                          const int64_t* M_have, int32_t mode, double target, int64_t* M_out,
                          int32_t* flag, void* stream);
 
+/* ---- learned control variate (not in the paper) ----------------------------
+ * A permutation-invariant set network over the bubbles of a cloud, used as an
+ * extra low-fidelity level of the OF-MLMC estimator whose optimal coefficient
+ * (eq. (alpha-matvec)) absorbs its error:
+ *   phi(x) = ReLU(W2 ReLU(W1 x + b1) + b2)     per bubble, 4 -> 128 -> 128
+ *   s      = pool_scale * sum over the set's bubbles of phi(x)
+ *   y      = W4 ReLU(W3 s + b3) + b4            128 -> 128 -> 5, standardised
+ *   output = y * out_std + out_mean             (p_max, x*, y*, z*, t*)
+ * The 128-wide contractions (forward and backward) run on the matrix cores
+ * with bf16 operands (round to nearest even) and float accumulation; the rest
+ * is float.  Parameters are float masters, flat, in the order W1[128][4],
+ * b1[128], W2[128][128], b2[128], W3[128][128], b3[128], W4[5][128], b4[5]
+ * (W[out][in]).  Training minimises the mean squared error of the
+ * standardised outputs with Adam.  Set inputs: x [dev] rows x 4 floats,
+ * offsets [dev] n_sets + 1 ints (set i is rows offsets[i] .. offsets[i+1]-1).
+ * All calls enqueue on `stream`; those taking offsets read offsets[n_sets]
+ * back to the host (synchronising the stream). */
+typedef struct ofm_nn ofm_nn;
+
+typedef struct {
+    int32_t d_in, width, d_out, reserved;  /* 4, 128, 5 */
+    float pool_scale;                      /* 1 / (reference number of bubbles) */
+    float lr, beta1, beta2, adam_eps, reserved2;
+    float out_mean[5], out_std[5];         /* standardisation of the outputs */
+} ofm_nn_spec;
+
+/* Create a network on the current device with He-uniform weights drawn
+ * from SplitMix64(seed ^ parameter index), zero biases. */
+int ofm_nn_create(ofm_ctx* ctx, const ofm_nn_spec* spec, uint64_t seed, ofm_nn** out);
+void ofm_nn_destroy(ofm_nn* nn);
+int64_t ofm_nn_param_count(void);
+/* params [dev] ofm_nn_param_count() floats */
+int ofm_nn_get_params(ofm_nn* nn, float* params, void* stream);
+int ofm_nn_set_params(ofm_nn* nn, const float* params, void* stream);
+/* mean, std [dev] 5 floats each */
+int ofm_nn_set_normalization(ofm_nn* nn, const float* mean, const float* std_dev, void* stream);
+int ofm_nn_reset_optimizer(ofm_nn* nn, void* stream);
+/* Per-bubble inputs ((c - center)/cloud_radius, ln(r/r_median)/r_sigma) of
+ * bubbles [dev] rows x 4 doubles into x [dev] rows x 4 floats. */
+int ofm_nn_features(const ofm_cloud_spec* spec, const double* bubbles, int64_t rows, float* x, void* stream);
+/* y [dev] n_sets x 5 floats, in physical units. */
+int ofm_nn_forward(ofm_nn* nn, const float* x, const int32_t* offsets, int32_t n_sets, float* y, void* stream);
+/* Loss (mean squared standardised error) [dev] 1 float and its gradient
+ * grads [dev, may be NULL] (parameter layout) for targets y_true [dev]
+ * n_sets x 5 in physical units; parameters unchanged. */
+int ofm_nn_grads(ofm_nn* nn, const float* x, const int32_t* offsets, int32_t n_sets, const float* y_true,
+                 float* grads, float* loss, void* stream);
+/* One Adam step on the batch (loss [dev] 1 float, before the step). */
+int ofm_nn_train_step(ofm_nn* nn, const float* x, const int32_t* offsets, int32_t n_sets, const float* y_true,
+                      float* loss, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

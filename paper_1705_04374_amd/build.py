@@ -31,6 +31,8 @@ SOURCES = [
     ("flow_kernels.hip", DEVICE),
     ("mlmc_kernels.hip", DEVICE),
     ("capi.hip", DEVICE),
+    ("nn_kernels.hip", DEVICE),
+    ("nn_api.hip", DEVICE),
     ("sampler.cpp", ["-ffp-contract=off"]),
 ]
 

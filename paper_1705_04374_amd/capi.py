@@ -28,6 +28,9 @@ EXPORTS = [
     "ofm_state_from_primitive", "ofm_state_to_conserved", "ofm_step", "ofm_solve", "ofm_solve_batch", "ofm_last_solve_stats",
     "ofm_mlmc_moments", "ofm_ofmlmc_coefficients", "ofm_ofmlmc_errors", "ofm_ofmlmc_estimate",
     "ofm_ofmlmc_optimal_M", "ofm_tune_set", "ofm_kernel_timing", "ofm_kernel_times",
+    "ofm_nn_create", "ofm_nn_destroy", "ofm_nn_param_count", "ofm_nn_get_params", "ofm_nn_set_params",
+    "ofm_nn_set_normalization", "ofm_nn_reset_optimizer", "ofm_nn_features", "ofm_nn_forward", "ofm_nn_grads",
+    "ofm_nn_train_step",
 ]
 
 
@@ -83,7 +86,8 @@ class BatchItem(C.Structure):
 class NNSpec(C.Structure):
     _fields_ = [("d_in", C.c_int32), ("width", C.c_int32), ("d_out", C.c_int32), ("reserved", C.c_int32),
                 ("pool_scale", C.c_float), ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
-                ("adam_eps", C.c_float), ("reserved2", C.c_float)]
+                ("adam_eps", C.c_float), ("reserved2", C.c_float),
+                ("out_mean", C.c_float * 5), ("out_std", C.c_float * 5)]
 
 
 _lib = None
@@ -121,15 +125,19 @@ def lib():
         L.ofm_tune_set.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32]
         L.ofm_kernel_timing.argtypes = [vp, i32]
         L.ofm_kernel_times.argtypes = [vp, C.POINTER(i64), dp, dp]
-        if hasattr(L, "ofm_nn_create"):
-            L.ofm_nn_create.argtypes = [vp, C.POINTER(NNSpec), C.c_uint64, C.POINTER(vp)]
-            L.ofm_nn_destroy.argtypes = [vp]
-            L.ofm_nn_destroy.restype = None
-            L.ofm_nn_get_params.argtypes = [vp, vp, vp]
-            L.ofm_nn_set_params.argtypes = [vp, vp, vp]
-            L.ofm_nn_forward.argtypes = [vp, vp, vp, i32, vp, vp]
-            L.ofm_nn_train_step.argtypes = [vp, vp, vp, i32, vp, vp, vp]
-            L.ofm_nn_grads.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
+        L.ofm_nn_create.argtypes = [vp, C.POINTER(NNSpec), C.c_uint64, C.POINTER(vp)]
+        L.ofm_nn_destroy.argtypes = [vp]
+        L.ofm_nn_destroy.restype = None
+        L.ofm_nn_param_count.argtypes = []
+        L.ofm_nn_param_count.restype = i64
+        L.ofm_nn_get_params.argtypes = [vp, vp, vp]
+        L.ofm_nn_set_params.argtypes = [vp, vp, vp]
+        L.ofm_nn_set_normalization.argtypes = [vp, vp, vp, vp]
+        L.ofm_nn_reset_optimizer.argtypes = [vp, vp]
+        L.ofm_nn_features.argtypes = [C.POINTER(CloudSpec), vp, i64, vp, vp]
+        L.ofm_nn_forward.argtypes = [vp, vp, vp, i32, vp, vp]
+        L.ofm_nn_grads.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp]
+        L.ofm_nn_train_step.argtypes = [vp, vp, vp, i32, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -317,3 +325,69 @@ def ofm_kernel_times(ctx: Context) -> dict:
     n, ms, cells = C.c_int64(), C.c_double(), C.c_double()
     ctx.check(lib().ofm_kernel_times(ctx.h, C.byref(n), C.byref(ms), C.byref(cells)))
     return dict(launches=n.value, total_ms=ms.value, cells=cells.value)
+
+
+class SetNet:
+    """The learned control variate (ofm_nn_* calls)."""
+
+    def __init__(self, ctx: Context, pool_scale: float, seed: int = 0, lr: float = 1e-3, beta1: float = 0.9,
+                 beta2: float = 0.999, adam_eps: float = 1e-8, out_mean=(0.0,) * 5, out_std=(1.0,) * 5):
+        sp = NNSpec()
+        sp.d_in, sp.width, sp.d_out = 4, 128, 5
+        sp.pool_scale, sp.lr, sp.beta1, sp.beta2, sp.adam_eps = pool_scale, lr, beta1, beta2, adam_eps
+        for i in range(5):
+            sp.out_mean[i] = out_mean[i]
+            sp.out_std[i] = out_std[i]
+        h = C.c_void_p()
+        ctx.check(lib().ofm_nn_create(ctx.h, C.byref(sp), seed, C.byref(h)))
+        self.h, self.ctx = h, ctx
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ofm_nn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        if rc != OFM_OK:
+            raise OfmError(rc, lib().ofm_last_error(None).decode())
+
+    @staticmethod
+    def param_count() -> int:
+        return int(lib().ofm_nn_param_count())
+
+    def get_params(self, out, stream=None):
+        self._chk(lib().ofm_nn_get_params(self.h, _dptr(out), _stream(stream)))
+
+    def set_params(self, p, stream=None):
+        self._chk(lib().ofm_nn_set_params(self.h, _dptr(p), _stream(stream)))
+
+    def set_normalization(self, mean, std, stream=None):
+        self._chk(lib().ofm_nn_set_normalization(self.h, _dptr(mean), _dptr(std), _stream(stream)))
+
+    def reset_optimizer(self, stream=None):
+        self._chk(lib().ofm_nn_reset_optimizer(self.h, _stream(stream)))
+
+    def forward(self, x, offsets, y, stream=None):
+        self._chk(lib().ofm_nn_forward(self.h, _dptr(x), _dptr(offsets), offsets.numel() - 1, _dptr(y),
+                                       _stream(stream)))
+
+    def grads(self, x, offsets, y_true, grads, loss, stream=None):
+        self._chk(lib().ofm_nn_grads(self.h, _dptr(x), _dptr(offsets), offsets.numel() - 1, _dptr(y_true),
+                                     _dptr(grads), _dptr(loss), _stream(stream)))
+
+    def train_step(self, x, offsets, y_true, loss, stream=None):
+        self._chk(lib().ofm_nn_train_step(self.h, _dptr(x), _dptr(offsets), offsets.numel() - 1, _dptr(y_true),
+                                          _dptr(loss), _stream(stream)))
+
+
+def ofm_nn_features(spec: dict, bubbles_dev, x_out, stream=None):
+    cs = cloud_spec(spec)
+    rc = lib().ofm_nn_features(C.byref(cs), _dptr(bubbles_dev), bubbles_dev.shape[0], _dptr(x_out), _stream(stream))
+    if rc != OFM_OK:
+        raise OfmError(rc, lib().ofm_last_error(None).decode())
