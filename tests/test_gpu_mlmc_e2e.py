@@ -1,0 +1,83 @@
+"""End to end: the two-level 2-D FP64 MLMC of the plain method (8 bubbles,
+32^2 with 16 samples, 64^2/32^2 with 4 coupled pairs, run to the end time)
+through the driver and the library, against the same pipeline built from the
+oracle (its sampler, its solver, its estimator)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle.flow as OF
+import oracle.mlmc as OM
+from oracle.sampler import sample_cloud
+from workloads.configs import MASTER_SEED, cloud_spec, solver_config, t_end
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def test_two_level_2d_fp64_against_oracle_pipeline(tmp_path):
+    from paper_1705_04374_amd import capi
+    from paper_1705_04374_amd.driver import OFMLMC
+    ctx = capi.Context(0)
+    T = t_end("cloud2d")
+    spec = cloud_spec("cloud2d")
+    cfg = solver_config("cloud2d", 32)
+    mc = OFMLMC(ctx, cfg, spec, [32, 64], "f64", t_end=T, seed=MASTER_SEED, ledger=str(tmp_path / "ledger.jsonl"))
+    say("gpu mlmc")
+    mc.sample(0, 16)
+    mc.sample(1, 4)
+    W = [1.0, 9.0]           # pair cost 64^3 + 32^3 in units of a 32^3 solve
+    res = mc.evaluate(W)
+    classical = mc.evaluate(W, classical=True)
+    say("oracle pipeline")
+    qf0, qf1, qc1 = [], [], []
+    for i in range(16):
+        b = sample_cloud(spec, MASTER_SEED, 0, i)
+        r = OF.solve(solver_config("cloud2d", 32), b, t_end=T)
+        assert r["status"] == 0
+        qf0.append(r["p_max"])
+    for i in range(4):
+        b = sample_cloud(spec, MASTER_SEED, 1, i)
+        qf1.append(OF.solve(solver_config("cloud2d", 64), b, t_end=T)["p_max"])
+        qc1.append(OF.solve(solver_config("cloud2d", 32), b, t_end=T)["p_max"])
+    # per-sample QoIs through the whole collapse (FP64).  Round-off grows
+    # through violent collapses (the 1e-10 field bar holds over 100 steps,
+    # test_gpu_flow), so full runs are held to: most samples to 1e-8, every
+    # sample to 1 %, and the reported differences are printed.
+    gpu = np.array(mc.q[0]["f"] + mc.q[1]["f"] + mc.q[1]["c"])
+    ora = np.array(qf0 + qf1 + qc1)
+    d = np.abs(gpu / ora - 1)
+    say("full-run QoI relative differences:", np.array2string(d, precision=2))
+    assert np.median(d) <= 1e-8 and d.max() <= 1e-2
+    assert all(mc.q[0]["ok"]) and all(mc.q[1]["ok"])
+    # the estimator on identical QoIs: the estimator bar (1e-12)
+    g0 = OM.term_moments(mc.q[0]["f"])
+    g1 = OM.term_moments(mc.q[1]["f"], mc.q[1]["c"])
+    ga = OM.coefficients([g0["Vf"], g1["Vf"]], [0.0, g1["Vc"]], [0.0, g1["C"]], W)
+    gE = OM.estimate([g0["mean_f"], g1["mean_f"]], [0.0, g1["mean_c"]], ga)
+    gs = OM.term_variances([g0["Vf"], g1["Vf"]], [0.0, g1["Vc"]], [0.0, g1["C"]], ga)
+    assert math.isclose(res["alpha"][0], ga[0], rel_tol=1e-12)
+    assert math.isclose(res["E"], gE, rel_tol=1e-12)
+    assert math.isclose(res["eps"], math.sqrt(OM.error2(gs, [16, 4])), rel_tol=1e-12)
+    # and the whole oracle pipeline
+    m0 = OM.term_moments(qf0)
+    m1 = OM.term_moments(qf1, qc1)
+    a = OM.coefficients([m0["Vf"], m1["Vf"]], [0.0, m1["Vc"]], [0.0, m1["C"]], W)
+    E = OM.estimate([m0["mean_f"], m1["mean_f"]], [0.0, m1["mean_c"]], a)
+    say("alpha", res["alpha"], a, "E", res["E"], E)
+    assert math.isclose(res["E"], E, rel_tol=1e-3)
+    # classical MLMC is the same estimator with alpha = 1
+    assert math.isclose(classical["E"], np.mean(mc.q[0]["f"]) + np.mean(mc.q[1]["f"]) - np.mean(mc.q[1]["c"]),
+                        rel_tol=1e-12)
+    # the ledger lets a second driver resume without solving again
+    mc2 = OFMLMC(ctx, cfg, spec, [32, 64], "f64", t_end=T, seed=MASTER_SEED, ledger=str(tmp_path / "ledger.jsonl"))
+    mc2.sample(0, 16)
+    mc2.sample(1, 4)
+    assert mc2.solve_seconds == 0.0
+    assert mc2.evaluate(W)["E"] == res["E"]
+    ctx.close()
