@@ -57,16 +57,24 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 side measurement")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-tune", action="store_true", help="use the default tile instead of autotuning")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy three times (reference for HBM byte counters)")
     return ap.parse_args()
 
 
-def measure(ctx, capi, cfg, bub, precision, steps, warmup):
+def measure(ctx, capi, cfg, bub, precision, steps, warmup, tune=True):
     import torch
     from paper_1705_04374_amd.state import alloc_state
     spec = capi.make_spec(cfg, precision, n_steps=steps)
     st, bufs = alloc_state(cfg, precision)
+    tuned = None
+    if tune:
+        # the library's autotuner times every compiled tile / z-chunk on this
+        # workload (2 steps each) and keeps the fastest; then start afresh
+        capi.ofm_state_init(ctx, spec, bub, st)
+        tuned = capi.ofm_autotune(ctx, spec, st, 2)
+        print("autotune %s: %s" % (precision, json.dumps(tuned)), file=sys.stderr, flush=True)
     capi.ofm_state_init(ctx, spec, bub, st)
     torch.cuda.synchronize()
     if warmup:
@@ -83,7 +91,7 @@ def measure(ctx, capi, cfg, bub, precision, steps, warmup):
     capi.ofm_kernel_timing(ctx, False)
     del bufs
     torch.cuda.empty_cache()
-    return dict(wall=wall, q=q, kt=kt)
+    return dict(wall=wall, q=q, kt=kt, tuned=tuned)
 
 
 def cpu_baseline(cfg, bub):
@@ -152,7 +160,7 @@ def main():
     bub = capi.ofm_sample_cloud(cloud_spec("cloud500"), MASTER_SEED, 0, 0)
     ctx = capi.Context(0)
     cells = n ** 3
-    r = measure(ctx, capi, cfg, bub, a.precision, a.steps, a.warmup)
+    r = measure(ctx, capi, cfg, bub, a.precision, a.steps, a.warmup, tune=not a.no_tune)
     ms_per_step = r["wall"] * 1e3 / a.steps
     value = cells * a.steps / r["wall"]
     kt = r["kt"]
@@ -175,6 +183,7 @@ def main():
         "frac": round(alu_frac if bound == "alu" else hbm_frac, 4),
         "traffic": None,
         "avg_launch_ms": round(avg_ms, 4),
+        "tile": None if r["tuned"] is None else {k: r["tuned"][k] for k in ("tx", "ty", "zchunk")},
         "hbm": {"achieved_GBs": round(gbs, 1), "peak_GBs": HBM_PEAK_GBS, "frac": round(hbm_frac, 4),
                 "algorithmic_bytes_per_launch": bytes_per_launch},
         "alu": {"achieved_TFLOPs": round(tfl, 2), "peak_TFLOPs": VALU_PEAK_TFLOPS[a.precision],
@@ -198,12 +207,13 @@ def main():
         "roofline": roof,
     }
     if not a.no_fp64 and a.precision == "f32":
-        r64 = measure(ctx, capi, cfg, bub, "f64", max(4, a.steps // 3), 1)
+        r64 = measure(ctx, capi, cfg, bub, "f64", max(4, a.steps // 3), 1, tune=not a.no_tune)
         kt64 = r64["kt"]
         ms64 = kt64["total_ms"] / max(kt64["launches"], 1)
         c64 = kt64["cells"] / max(kt64["launches"], 1)
         out["fp64"] = {"value": cells * max(4, a.steps // 3) / r64["wall"], "unit": "cell-updates/s",
                        "avg_stage_launch_ms": round(ms64, 4),
+                       "tile": None if r64["tuned"] is None else {k: r64["tuned"][k] for k in ("tx", "ty", "zchunk")},
                        "hbm_frac": round(c64 * WORDS_PER_CELL_STEP * 8 / 3.0 / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                        "alu_frac": round(c64 * FLOPS_PER_CELL_STAGE / (ms64 * 1e-3) / 1e12 / VALU_PEAK_TFLOPS["f64"], 4)}
     if not a.no_cpu:

@@ -230,6 +230,29 @@ int ofm_last_solve_stats(const ofm_ctx* ctx, double* init_s, double* step_s,
 int ofm_tune_set(ofm_ctx* ctx, int32_t precision, int32_t ndim, int32_t n, int32_t tx, int32_t ty,
                  int32_t zchunk, int32_t graph_steps);
 
+/* Result of ofm_autotune: the chosen tile and schedule, the summed duration
+ * of the three stage-kernel launches of one step with it (ms), and the number
+ * of candidates timed. */
+typedef struct ofm_tune_result {
+    int32_t tx, ty, zchunk, graph_steps;
+    double stage_ms_per_step;
+    int32_t candidates;
+    int32_t reserved;
+} ofm_tune_result;
+
+/* Measure every compiled tile shape (and, in 3-D, z-chunks of 8, 16, 32 and
+ * 64 planes not larger than n) of the stage kernel for spec's precision,
+ * dimension and grid, by stepping the caller's state st [dev] `steps` time
+ * steps per candidate with per-launch events, and store the fastest as the
+ * entry ofm_tune_set would write; out [host] receives it.  The state is
+ * advanced (candidates x steps steps, u and u_tmp may swap as in ofm_step):
+ * pass a scratch copy.  all [host, may be NULL] receives up to all_cap
+ * entries, one per candidate in the order timed (candidates = 1 each).  On
+ * an error the previous entry is kept; OFM_EINVAL also if the state fails
+ * (non-finite, c^2 <= 0) while stepping.  Synchronises the stream. */
+int ofm_autotune(ofm_ctx* ctx, const ofm_solve_spec* spec, ofm_state_view* st, int32_t steps,
+                 ofm_tune_result* out, ofm_tune_result* all, int32_t all_cap, void* stream);
+
 /* Per-kernel timing for profiling: while enabled, solves launch their steps
  * one by one (no graphs) and bracket every stage-kernel launch with HIP events
  * on the stream the kernel runs on.  ofm_kernel_times returns, since the last

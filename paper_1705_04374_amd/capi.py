@@ -27,7 +27,7 @@ EXPORTS = [
     "ofm_ctx_create", "ofm_ctx_destroy", "ofm_last_error", "ofm_sample_cloud", "ofm_state_init",
     "ofm_state_from_primitive", "ofm_state_to_conserved", "ofm_step", "ofm_solve", "ofm_solve_batch", "ofm_last_solve_stats",
     "ofm_mlmc_moments", "ofm_ofmlmc_coefficients", "ofm_ofmlmc_errors", "ofm_ofmlmc_estimate",
-    "ofm_ofmlmc_optimal_M", "ofm_tune_set", "ofm_kernel_timing", "ofm_kernel_times",
+    "ofm_ofmlmc_optimal_M", "ofm_tune_set", "ofm_autotune", "ofm_kernel_timing", "ofm_kernel_times",
     "ofm_nn_create", "ofm_nn_destroy", "ofm_nn_param_count", "ofm_nn_get_params", "ofm_nn_set_params",
     "ofm_nn_set_normalization", "ofm_nn_reset_optimizer", "ofm_nn_features", "ofm_nn_forward", "ofm_nn_grads",
     "ofm_nn_train_step",
@@ -83,6 +83,11 @@ class BatchItem(C.Structure):
                 ("reserved", C.c_int32)]
 
 
+class TuneResult(C.Structure):
+    _fields_ = [("tx", C.c_int32), ("ty", C.c_int32), ("zchunk", C.c_int32), ("graph_steps", C.c_int32),
+                ("stage_ms_per_step", C.c_double), ("candidates", C.c_int32), ("reserved", C.c_int32)]
+
+
 class NNSpec(C.Structure):
     _fields_ = [("d_in", C.c_int32), ("width", C.c_int32), ("d_out", C.c_int32), ("reserved", C.c_int32),
                 ("pool_scale", C.c_float), ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
@@ -123,6 +128,8 @@ def lib():
         L.ofm_ofmlmc_estimate.argtypes = [vp, i32, vp, vp, vp, vp]
         L.ofm_ofmlmc_optimal_M.argtypes = [vp, i32, vp, vp, vp, i32, C.c_double, vp, vp, vp]
         L.ofm_tune_set.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32]
+        L.ofm_autotune.argtypes = [vp, C.POINTER(SolveSpec), C.POINTER(StateView), i32, C.POINTER(TuneResult),
+                                   C.POINTER(TuneResult), i32, vp]
         L.ofm_kernel_timing.argtypes = [vp, i32]
         L.ofm_kernel_times.argtypes = [vp, C.POINTER(i64), dp, dp]
         L.ofm_nn_create.argtypes = [vp, C.POINTER(NNSpec), C.c_uint64, C.POINTER(vp)]
@@ -315,6 +322,19 @@ def ofm_ofmlmc_optimal_M(ctx: Context, L: int, sig, W, have, mode: int, target: 
 def ofm_tune_set(ctx: Context, precision: int, ndim: int, n: int, tx: int, ty: int, zchunk: int,
                  graph_steps: int):
     ctx.check(lib().ofm_tune_set(ctx.h, precision, ndim, n, tx, ty, zchunk, graph_steps))
+
+
+def ofm_autotune(ctx: Context, spec: SolveSpec, st: StateView, steps: int = 2, stream=None) -> dict:
+    """Time the compiled tile shapes / z-chunks on the (scratch) state st and
+    keep the fastest for spec's precision, dimension and size class."""
+    r = TuneResult()
+    cap = 64
+    every = (TuneResult * cap)()
+    ctx.check(lib().ofm_autotune(ctx.h, C.byref(spec), C.byref(st), steps, C.byref(r), every, cap,
+                                 _stream(stream)))
+    return dict(tx=r.tx, ty=r.ty, zchunk=r.zchunk, graph_steps=r.graph_steps,
+                stage_ms_per_step=r.stage_ms_per_step, candidates=r.candidates,
+                table=[(e.tx, e.ty, e.zchunk, e.stage_ms_per_step) for e in every[:min(r.candidates, cap)]])
 
 
 def ofm_kernel_timing(ctx: Context, enable: bool):

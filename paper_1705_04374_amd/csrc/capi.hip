@@ -562,6 +562,69 @@ int ofm_tune_set(ofm_ctx* ctx, int32_t precision, int32_t ndim, int32_t n, int32
     return OFM_OK;
 }
 
+int ofm_autotune(ofm_ctx* ctx, const ofm_solve_spec* spec, ofm_state_view* st, int32_t steps,
+                 ofm_tune_result* out, ofm_tune_result* all, int32_t all_cap, void* stream)
+{
+    if (!ctx) return fail(nullptr, OFM_EINVAL, "null context");
+    int rc = validate(ctx, spec);
+    if (rc) return rc;
+    if (!st || !st->u || !st->u_tmp || !st->du || steps < 1 || steps > 1000 || !out || all_cap < 0 ||
+        (all_cap > 0 && !all))
+        return fail(ctx, OFM_EINVAL, "ofm_autotune: bad arguments");
+    int tiles[32][2];
+    const int nt = std::min(tile_list(spec->precision, spec->ndim, tiles, 32), 32);
+    std::vector<int> zcs;
+    if (spec->ndim == 3) {
+        for (int z : { 8, 16, 32, 64 })
+            if (z <= spec->n) zcs.push_back(z);
+        if (zcs.empty()) zcs.push_back(spec->n);
+    } else {
+        zcs.push_back(1);
+    }
+    const TileChoice before = ctx->tuning.choose(spec->precision, spec->ndim, spec->n, 1);
+    const bool had_timing = ctx->timing;
+    const int64_t l0 = ctx->t_launches;
+    const double m0 = ctx->t_ms, c0 = ctx->t_cells;
+    TileChoice best = before;
+    double best_ms = INFINITY;
+    int tried = 0;
+    ofm_qoi q;
+    for (int i = 0; i < nt && rc == OFM_OK; ++i)
+        for (int z : zcs) {
+            ctx->tuning.set(spec->precision, spec->ndim, spec->n, TileChoice{ tiles[i][0], tiles[i][1], z, 2 });
+            ctx->timing = true;
+            ctx->t_launches = 0;
+            ctx->t_ms = 0.0;
+            ctx->t_cells = 0.0;
+            rc = ofm_step(ctx, spec, st, steps, &q, nullptr, stream);
+            if (rc == OFM_OK && q.status != OFM_SAMPLE_OK)
+                rc = fail(ctx, OFM_EINVAL, "ofm_autotune: the state failed while stepping (status %d)", q.status);
+            if (rc) break;
+            const double ms = ctx->t_ms * 3.0 / (double)std::max<int64_t>(ctx->t_launches, 1);
+            if (tried < all_cap)
+                all[tried] = ofm_tune_result{ tiles[i][0], tiles[i][1], z, before.graph_steps, ms, 1, 0 };
+            ++tried;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = TileChoice{ tiles[i][0], tiles[i][1], z, before.graph_steps };
+            }
+        }
+    ctx->timing = had_timing;
+    ctx->t_launches = l0;
+    ctx->t_ms = m0;
+    ctx->t_cells = c0;
+    ctx->tuning.set(spec->precision, spec->ndim, spec->n, rc == OFM_OK ? best : before);
+    if (rc) return rc;
+    out->tx = best.tx;
+    out->ty = best.ty;
+    out->zchunk = best.zchunk;
+    out->graph_steps = best.graph_steps;
+    out->stage_ms_per_step = best_ms;
+    out->candidates = tried;
+    out->reserved = 0;
+    return OFM_OK;
+}
+
 int ofm_kernel_timing(ofm_ctx* ctx, int32_t enable)
 {
     if (!ctx) return fail(nullptr, OFM_EINVAL, "null context");

@@ -17,6 +17,8 @@ struct InitLaunch {
 };
 
 bool tile_supported(int precision, int ndim, int tx, int ty);
+// compiled tile shapes of (precision, ndim): up to cap (tx, ty) pairs; returns the count
+int tile_list(int precision, int ndim, int (*out)[2], int cap);
 hipError_t launch_stage(int precision, int ndim, int tx, int ty, const LaunchArgs& a, int stage, hipStream_t s);
 hipError_t launch_reduce(int precision, int ndim, int tx, int ty, const LaunchArgs& a, hipStream_t s);
 hipError_t launch_finalize(const SampleDesc* desc, SampleState* state, const TilePartial* part, int n_samples,

@@ -42,23 +42,46 @@ namespace ofm {
 template <typename T> struct Num;
 template <> struct Num<float> {
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float fma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
     static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+    // sqrt(a / b) for a, b > 0 with one transcendental: a / sqrt(a b)
+    static __device__ __forceinline__ float sqrt_ratio(float a, float b) { return a * __builtin_amdgcn_rsqf(a * b); }
     // round-off allowance of the positivity checks, relative to the stencil
     static constexpr float round_tol = 1e-6f;
 };
 template <> struct Num<double> {
-    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    // hardware reciprocal estimate refined by two Newton steps
+    // r <- r + r (1 - x r): within an ulp or two of 1/x for the finite,
+    // nonzero, normal x this code divides by
+    static __device__ __forceinline__ double rcp(double x)
+    {
+        double r = __builtin_amdgcn_rcp(x);
+        r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+        return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    }
+    static __device__ __forceinline__ double fma(double a, double b, double c) { return __builtin_fma(a, b, c); }
     static __device__ __forceinline__ double sqrt_(double x) { return ::sqrt(x); }
+    // sqrt(a / b) = a / sqrt(a b) for a, b > 0: reciprocal square root
+    // estimate refined by two Newton steps y <- y (3/2 - (x/2) y^2)
+    static __device__ __forceinline__ double sqrt_ratio(double a, double b)
+    {
+        const double x = a * b, h = 0.5 * x;
+        double y = __builtin_amdgcn_rsq(x);
+        y = y * __builtin_fma(-h, y * y, 1.5);
+        y = y * __builtin_fma(-h, y * y, 1.5);
+        return a * y;
+    }
     static constexpr double round_tol = 1e-12;
 };
 
 template <typename T> struct Phys {
-    T g1inv, dginv, pi1, dpi, eps;
+    T g1inv, dginv, pi1, dpi;
+    T eps;             // (12/13) x the WENO epsilon (the indicators' scale in weno5_cell)
     T gam1, pc1, gam2, pc2;
     T rho1, rho2;      // reference phase densities (scale of the positivity checks)
     __device__ __forceinline__ explicit Phys(const PhysD& d)
         : g1inv((T)d.g1inv), dginv((T)(d.g2inv - d.g1inv)), pi1((T)d.pi1), dpi((T)(d.pi2 - d.pi1)),
-          eps((T)d.eps), gam1((T)d.gamma1), pc1((T)d.pc1), gam2((T)d.gamma2), pc2((T)d.pc2),
+          eps((T)(d.eps * (12.0 / 13.0))), gam1((T)d.gamma1), pc1((T)d.pc1), gam2((T)d.gamma2), pc2((T)d.pc2),
           rho1((T)d.rho1), rho2((T)d.rho2) {}
     // mixture stiffened-gas coefficients under isobaric closure:
     // p = (E - rho|u|^2/2 - Pi(a2)) / Gamma(a2)
@@ -96,43 +119,47 @@ __device__ __forceinline__ void to_prim(const Phys<T>& ph, const T* q, T* w)
 // invariant under adding a constant to the stencil, so it is evaluated on the
 // differences from the centre value (exact in exact arithmetic; in float it
 // keeps the rounding of large offsets, such as 1e7 Pa, out of the weights and
-// candidate values).  The two edges share the smoothness indicators; the
-// nonlinear weights are normalised by the smallest (eps + beta) so that they
-// cannot overflow (same weights).
+// candidate values).  The two edges share the smoothness indicators.
+//
+// Arithmetic forms (each equal to the textbook one in exact arithmetic):
+//  * the indicators are carried as (12/13) beta_k = t0^2 + (sqrt(3/13) t1)^2
+//    with eps_s = (12/13) eps (Phys::eps holds eps_s), which leaves every
+//    ratio (eps + beta_j) / (eps + beta_k), hence every weight, unchanged;
+//  * the nonlinear weights are normalised by the smallest (eps + beta), so
+//    that they cannot overflow, and the two weight sums, both in [0.1, 1],
+//    share one reciprocal;
+//  * the candidate values are carried times 6 and the 1/6 is applied with
+//    that reciprocal.
 template <typename T>
-__device__ __forceinline__ void weno5_cell(T a, T b, T c, T d, T e, T eps, T& lo, T& hi)
+__device__ __forceinline__ void weno5_cell(T a, T b, T c, T d, T e, T eps_s, T& lo, T& hi)
 {
-    const T k13 = T(13) / T(12), k6 = T(1) / T(6);
-    a -= c;
-    b -= c;
-    d -= c;
-    e -= c;
-    T t0 = a - T(2) * b, t1 = a - T(4) * b;
-    T b0 = k13 * t0 * t0 + T(0.25) * t1 * t1;
-    t0 = b + d;
-    t1 = b - d;
-    T b1 = k13 * t0 * t0 + T(0.25) * t1 * t1;
-    t0 = e - T(2) * d;
-    t1 = e - T(4) * d;
-    T b2 = k13 * t0 * t0 + T(0.25) * t1 * t1;
-    T e0 = eps + b0, e1 = eps + b1, e2 = eps + b2;
-    T m = fmin(fmin(e0, e1), e2);
-    T r0 = m * Num<T>::rcp(e0), r1 = m * Num<T>::rcp(e1), r2 = m * Num<T>::rcp(e2);
-    T q0 = r0 * r0, q1 = r1 * r1, q2 = r2 * r2;
-    // right edge: candidate values on stencils (a,b,c), (b,c,d), (c,d,e)
-    T p0 = (T(2) * a - T(7) * b) * k6;
-    T p1 = (T(2) * d - b) * k6;
-    T p2 = (T(5) * d - e) * k6;
-    T w0 = T(0.1) * q0, w1 = T(0.6) * q1, w2 = T(0.3) * q2;
-    hi = c + (w0 * p0 + w1 * p1 + w2 * p2) * Num<T>::rcp(w0 + w1 + w2);
-    // left edge: the mirrored stencil, whose indicators are (b2, b1, b0)
-    p0 = (T(2) * e - T(7) * d) * k6;
-    p1 = (T(2) * b - d) * k6;
-    p2 = (T(5) * b - a) * k6;
-    w0 = T(0.1) * q2;
-    w1 = T(0.6) * q1;
-    w2 = T(0.3) * q0;
-    lo = c + (w0 * p0 + w1 * p1 + w2 * p2) * Num<T>::rcp(w0 + w1 + w2);
+    const T s3 = T(0.48038446141526137);     // sqrt(3/13)
+    const T A = a - c, B = b - c, D = d - c, E = e - c;
+    // stencils (a,b,c), (b,c,d), (c,d,e): t0 = A - 2B, t1 = A - 4B, ...
+    T t0 = Num<T>::fma(B, T(-2), A);
+    T u = Num<T>::fma(A, s3, B * (T(-4) * s3));
+    const T e0 = Num<T>::fma(t0, t0, Num<T>::fma(u, u, eps_s));
+    t0 = B + D;
+    u = (B - D) * s3;
+    const T e1 = Num<T>::fma(t0, t0, Num<T>::fma(u, u, eps_s));
+    t0 = Num<T>::fma(D, T(-2), E);
+    u = Num<T>::fma(E, s3, D * (T(-4) * s3));
+    const T e2 = Num<T>::fma(t0, t0, Num<T>::fma(u, u, eps_s));
+    const T m = fmin(fmin(e0, e1), e2);
+    const T r0 = m * Num<T>::rcp(e0), r1 = m * Num<T>::rcp(e1), r2 = m * Num<T>::rcp(e2);
+    const T q0 = r0 * r0, q2 = r2 * r2;
+    // linear weights (1/10, 6/10, 3/10) at the right edge, mirrored at the left
+    const T wh0 = T(0.1) * q0, w1 = T(0.6) * (r1 * r1), wh2 = T(0.3) * q2;
+    const T wl0 = T(0.1) * q2, wl2 = T(0.3) * q0;
+    // 6 x candidate values: right edge (2A - 7B, 2D - B, 5D - E), left edge mirrored
+    const T ph0 = Num<T>::fma(A, T(2), B * T(-7)), ph1 = Num<T>::fma(D, T(2), -B), ph2 = Num<T>::fma(D, T(5), -E);
+    const T pl0 = Num<T>::fma(E, T(2), D * T(-7)), pl1 = Num<T>::fma(B, T(2), -D), pl2 = Num<T>::fma(B, T(5), -A);
+    const T nh = Num<T>::fma(wh0, ph0, Num<T>::fma(w1, ph1, wh2 * ph2));
+    const T nl = Num<T>::fma(wl0, pl0, Num<T>::fma(w1, pl1, wl2 * pl2));
+    const T sh = wh0 + w1 + wh2, sl = wl0 + w1 + wl2;
+    const T r = Num<T>::rcp(sh * sl) * T(1.0 / 6.0);
+    hi = Num<T>::fma(nh, sl * r, c);
+    lo = Num<T>::fma(nl, sh * r, c);
 }
 
 // Edges of one cell along one axis with the positivity / bounds checks.
@@ -200,8 +227,8 @@ __device__ __forceinline__ void hllc(const Phys<T>& ph, const T (&wl)[4 + ND], c
     // energies without Pi (its flux Pi(a2_K) u_f is added by the caller's source)
     T El = gl * pl + T(0.5) * rl * kel;
     T Er = gr * pr + T(0.5) * rr * ker;
-    T cl = Num<T>::sqrt_(((gl + T(1)) * pl + Pl) * Num<T>::rcp(gl * rl));
-    T cr = Num<T>::sqrt_(((gr + T(1)) * pr + Pr) * Num<T>::rcp(gr * rr));
+    T cl = Num<T>::sqrt_ratio((gl + T(1)) * pl + Pl, gl * rl);
+    T cr = Num<T>::sqrt_ratio((gr + T(1)) * pr + Pr, gr * rr);
     T sl = fmin(ul - cl, ur - cr);
     T sr = fmax(ul + cl, ur + cr);
     T ml = rl * (sl - ul), mr = rr * (sr - ur);
@@ -218,8 +245,8 @@ __device__ __forceinline__ void hllc(const Phys<T>& ph, const T (&wl)[4 + ND], c
     const T p = left ? pl : pr;
     const T E = left ? El : Er;
     const bool star = sk != T(0);
-    const T dK = star ? (sK - un) : T(1);
-    const T chi = star ? dK * Num<T>::rcp(sK - ss) : T(1);
+    const T rs = star ? Num<T>::rcp(sK - ss) : T(0);
+    const T chi = star ? (sK - un) * rs : T(1);
     f[0] = w[0] * un;
     f[1] = w[1] * un;
 #pragma unroll
@@ -234,7 +261,8 @@ __device__ __forceinline__ void hllc(const Phys<T>& ph, const T (&wl)[4 + ND], c
         f[2 + m] += sk * (qs - rho * w[2 + m]);
     }
     {
-        T Es = chi * (E + (ss - un) * (rho * ss + p * Num<T>::rcp(dK)));
+        // chi p / (S_K - u) = p / (S_K - S*)
+        T Es = chi * (E + (ss - un) * rho * ss) + (ss - un) * p * rs;
         f[2 + ND] += sk * (Es - E);
     }
     T uf = un + sk * (chi - T(1));
@@ -354,28 +382,44 @@ __constant__ double c_rk_b[3] = { 0.25, 8.0 / 9.0, 0.75 };
 // ---------------------------------------------------------------------------
 // Fused right-hand side + low-storage RK stage (+ reduction at stage 3)
 // ---------------------------------------------------------------------------
+constexpr int round_up64(int x) { return (x + 63) / 64 * 64; }
+
+// Threads per workgroup of a TX x TY tile: the cell count rounded up to whole
+// wavefronts (threads past the last cell help with the x-y tasks only).
+template <int TX, int TY> constexpr int stage_threads() { return round_up64(TX * TY); }
+
+// Occupancy target of the stage kernel: three wavefronts per SIMD for the
+// float kernels (at most 168 VGPRs), one for double.
+template <typename T> constexpr int stage_waves_per_eu() { return sizeof(T) == 4 ? 3 : 1; }
+
 template <typename T, int ND, int TX, int TY>
-__global__ void __launch_bounds__(TX * TY)
+__global__ void __launch_bounds__((stage_threads<TX, TY>()))
+__attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<T>())))
 stage_kernel(LaunchArgs a, int stage)
 {
     constexpr int NV = 4 + ND;
-    constexpr int NT = TX * TY;
+    constexpr int NT = stage_threads<TX, TY>();
     constexpr int HX = TX + 6;
     constexpr int HY = ND >= 2 ? TY + 6 : 1;
-    constexpr int EXN = TY * (TX + 2);                 // x edge tasks
-    constexpr int EYN = ND >= 2 ? (TY + 2) * TX : 0;   // y edge tasks
-    constexpr int FXN = TY * (TX + 1);
-    constexpr int FYN = ND >= 2 ? (TY + 1) * TX : 0;
+    // Task lists of the x-y phases.  The x block is padded to whole
+    // wavefronts so that no wavefront holds both x and y tasks (which would
+    // run both code paths under a split exec mask).
+    constexpr int EXN = TY * (TX + 2);                         // x edge tasks
+    constexpr int EXP = ND >= 2 ? round_up64(EXN) : EXN;       // start of the y edge tasks
+    constexpr int EYN = ND >= 2 ? (TY + 2) * TX : 0;           // y edge tasks
+    constexpr int ES = EXP + EYN;
+    constexpr int FXN = TY * (TX + 1);                         // x faces
+    constexpr int FXP = ND >= 2 ? round_up64(FXN) : FXN;       // start of the y faces
+    constexpr int FYN = ND >= 2 ? (TY + 1) * TX : 0;           // y faces
+    constexpr int FS = FXP + FYN;
     constexpr int WSZ = NV * HX * HY;
-    constexpr int FSZ = (NV + 1) * (FXN + FYN);
+    constexpr int FSZ = (NV + 1) * FS;
     constexpr int AL = WSZ > FSZ ? WSZ : FSZ;          // W plane and face fluxes share LDS
-    __shared__ T smem[AL + 2 * NV * (EXN + EYN)];
+    __shared__ T smem[AL + 2 * NV * ES];
     T* sW = smem;                          // [NV][HY][HX]
-    T* sFx = smem;                         // [NV+1][FXN]   (after the edges are built)
-    T* sFy = smem + (NV + 1) * FXN;        // [NV+1][FYN]
-    T* sEm = smem + AL;                    // left edges  [NV][EXN + EYN]
-    T* sEp = sEm + NV * (EXN + EYN);       // right edges [NV][EXN + EYN]
-    constexpr int ES = EXN + EYN;
+    T* sF = smem;                          // [NV+1][FS]   (after the edges are built)
+    T* sEm = smem + AL;                    // left edges  [NV][ES]
+    T* sEp = sEm + NV * ES;                // right edges [NV][ES]
 
     const int wi = xcd_swizzle(blockIdx.x, gridDim.x);
     if (wi >= a.n_work) return;
@@ -387,13 +431,14 @@ stage_kernel(LaunchArgs a, int stage)
     const Phys<T> ph(a.ph);
     const int n = d.n;
     const int tid = threadIdx.x;
-    const int tx = tid % TX, ty = tid / TX;
+    // cell of this thread; threads past the tile shadow its last row
+    const int tx = tid % TX, ty = min(tid / TX, TY - 1);
     const int ttx = item.tile % d.ntx;
     const int tty = (item.tile / d.ntx) % d.nty;
     const int tzc = item.tile / (d.ntx * d.nty);
     const int x0 = ttx * TX, y0 = tty * TY;
     const int gx = x0 + tx, gy = y0 + ty;
-    const bool mine = gx < n && (ND < 2 || gy < n);
+    const bool mine = tid < TX * TY && gx < n && (ND < 2 || gy < n);
     const int64_t ncell = ND == 3 ? (int64_t)n * n * n : (ND == 2 ? (int64_t)n * n : (int64_t)n);
     const int64_t plane = ND >= 2 ? (int64_t)n * n : (int64_t)n;
     const T* __restrict__ ua = (const T*)d.buf[a.src];
@@ -429,15 +474,16 @@ stage_kernel(LaunchArgs a, int stage)
     auto plane_xy = [&](T (&xy)[NV + 1]) {
         // edges along x of cells -1..TX of every row, along y of rows -1..TY
         for (int e = tid; e < ES; e += NT) {
+            if (e >= EXN && e < EXP) continue;             // padding of the x block
             T s[5][NV], lo[NV], hi[NV];
-            if (e < EXN) {
+            if (e < EXP) {
                 const int row = e / (TX + 2), cx = e % (TX + 2) - 1;
 #pragma unroll
                 for (int k = 0; k < 5; ++k)
 #pragma unroll
                     for (int v = 0; v < NV; ++v) s[k][v] = sW[(v * HY + row + (ND >= 2 ? 3 : 0)) * HX + cx + 1 + k];
             } else {
-                const int f = e - EXN;
+                const int f = e - EXP;
                 const int cy = f / TX - 1, col = f % TX;
 #pragma unroll
                 for (int k = 0; k < 5; ++k)
@@ -450,9 +496,10 @@ stage_kernel(LaunchArgs a, int stage)
         }
         __syncthreads();
         // faces: x faces i-1/2 (i = 0..TX) of every row, y faces j-1/2
-        for (int f = tid; f < FXN + FYN; f += NT) {
+        for (int f = tid; f < FS; f += NT) {
+            if (f >= FXN && f < FXP) continue;             // padding of the x block
             T wl[NV], wr[NV], fl[NV + 1];
-            if (f < FXN) {
+            if (f < FXP) {
                 const int row = f / (TX + 1), i = f % (TX + 1);
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
@@ -460,33 +507,31 @@ stage_kernel(LaunchArgs a, int stage)
                     wr[v] = sEm[v * ES + row * (TX + 2) + i + 1];
                 }
                 hllc<T, ND, 0>(ph, wl, wr, fl);
-#pragma unroll
-                for (int v = 0; v <= NV; ++v) sFx[v * FXN + f] = fl[v];
             } else {
                 if constexpr (ND >= 2) {
-                    const int g = f - FXN;
+                    const int g = f - FXP;
                     const int j = g / TX, col = g % TX;
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
-                        wl[v] = sEp[v * ES + EXN + j * TX + col];
-                        wr[v] = sEm[v * ES + EXN + (j + 1) * TX + col];
+                        wl[v] = sEp[v * ES + EXP + j * TX + col];
+                        wr[v] = sEm[v * ES + EXP + (j + 1) * TX + col];
                     }
                     hllc<T, ND, 1 < ND ? 1 : 0>(ph, wl, wr, fl);
-#pragma unroll
-                    for (int v = 0; v <= NV; ++v) sFy[v * FYN + g] = fl[v];
                 }
             }
+#pragma unroll
+            for (int v = 0; v <= NV; ++v) sF[v * FS + f] = fl[v];
         }
         __syncthreads();
         const int fx = ty * (TX + 1) + tx;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) xy[v] = sFx[v * FXN + fx] - sFx[v * FXN + fx + 1];
-        xy[NV] = sFx[NV * FXN + fx + 1] - sFx[NV * FXN + fx];
+        for (int v = 0; v < NV; ++v) xy[v] = sF[v * FS + fx] - sF[v * FS + fx + 1];
+        xy[NV] = sF[NV * FS + fx + 1] - sF[NV * FS + fx];
         if constexpr (ND >= 2) {
-            const int fy = ty * TX + tx;
+            const int fy = FXP + ty * TX + tx;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) xy[v] += sFy[v * FYN + fy] - sFy[v * FYN + fy + TX];
-            xy[NV] += sFy[NV * FYN + fy + TX] - sFy[NV * FYN + fy];
+            for (int v = 0; v < NV; ++v) xy[v] += sF[v * FS + fy] - sF[v * FS + fy + TX];
+            xy[NV] += sF[NV * FS + fy + TX] - sF[NV * FS + fy];
         }
     };
 
@@ -594,16 +639,17 @@ stage_kernel(LaunchArgs a, int stage)
 // Reduction of a state without stepping (initial level)
 // ---------------------------------------------------------------------------
 template <typename T, int ND, int TX, int TY>
-__global__ void __launch_bounds__(TX * TY) reduce_kernel(LaunchArgs a)
+__global__ void __launch_bounds__((stage_threads<TX, TY>())) reduce_kernel(LaunchArgs a)
 {
     constexpr int NV = 4 + ND;
+    constexpr int NT = stage_threads<TX, TY>();
     const int wi = xcd_swizzle(blockIdx.x, gridDim.x);
     if (wi >= a.n_work) return;
     const WorkItem item = a.work[wi];
     const SampleDesc& d = a.desc[item.sample];
     if (a.state[item.sample].done) return;
     const int n = d.n;
-    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;   // ty >= TY: no cell
     const int ttx = item.tile % d.ntx, tty = (item.tile / d.ntx) % d.nty, tzc = item.tile / (d.ntx * d.nty);
     const int gx = ttx * TX + tx, gy = tty * TY + ty;
     const int64_t ncell = ND == 3 ? (int64_t)n * n * n : (ND == 2 ? (int64_t)n * n : (int64_t)n);
@@ -611,7 +657,7 @@ __global__ void __launch_bounds__(TX * TY) reduce_kernel(LaunchArgs a)
     const T* u = (const T*)d.buf[a.src];
     Red red;
     red.init();
-    if (gx < n && (ND < 2 || gy < n)) {
+    if (ty < TY && gx < n && (ND < 2 || gy < n)) {
         const int z0 = ND == 3 ? tzc * a.zchunk : 0;
         const int z1 = ND == 3 ? min(z0 + a.zchunk, n) : 1;
         for (int z = z0; z < z1; ++z) {
@@ -622,7 +668,7 @@ __global__ void __launch_bounds__(TX * TY) reduce_kernel(LaunchArgs a)
             reduce_cell<T, ND>(a.ph, q, idx, red);
         }
     }
-    write_partial<TX * TY>(red, a.part + d.tile0 + item.tile);
+    write_partial<NT>(red, a.part + d.tile0 + item.tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -848,22 +894,22 @@ __global__ void __launch_bounds__(256) to_conserved_kernel(PhysD ph, const T* u,
 template <typename T, int ND, int TX, int TY>
 static hipError_t launch_stage_t(const LaunchArgs& a, int stage, hipStream_t s)
 {
-    hipLaunchKernelGGL((stage_kernel<T, ND, TX, TY>), dim3(a.n_work), dim3(TX * TY), 0, s, a, stage);
+    hipLaunchKernelGGL((stage_kernel<T, ND, TX, TY>), dim3(a.n_work), dim3(stage_threads<TX, TY>()), 0, s, a, stage);
     return hipGetLastError();
 }
 
 template <typename T, int ND, int TX, int TY>
 static hipError_t launch_reduce_t(const LaunchArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL((reduce_kernel<T, ND, TX, TY>), dim3(a.n_work), dim3(TX * TY), 0, s, a);
+    hipLaunchKernelGGL((reduce_kernel<T, ND, TX, TY>), dim3(a.n_work), dim3(stage_threads<TX, TY>()), 0, s, a);
     return hipGetLastError();
 }
 
 // Tile shapes compiled for each (precision, dimension).
-#define OFM_FOR_TILES(X)                                                        \
-    X(float, 3, 16, 16) X(float, 3, 32, 8) X(float, 3, 16, 8)                  \
-    X(double, 3, 16, 8) X(double, 3, 16, 16) X(double, 3, 8, 8)                \
-    X(float, 2, 16, 16) X(float, 2, 32, 8) X(double, 2, 16, 16) X(double, 2, 16, 8) \
+#define OFM_FOR_TILES(X)                                                               \
+    X(float, 3, 16, 14) X(float, 3, 16, 16) X(float, 3, 16, 8)                         \
+    X(double, 3, 16, 8) X(double, 3, 16, 14) X(double, 3, 8, 8)                        \
+    X(float, 2, 16, 14) X(float, 2, 16, 16) X(double, 2, 16, 14) X(double, 2, 16, 8)   \
     X(float, 1, 256, 1) X(double, 1, 256, 1) X(float, 1, 64, 1) X(double, 1, 64, 1)
 
 bool tile_supported(int precision, int ndim, int tx, int ty)
@@ -873,6 +919,19 @@ bool tile_supported(int precision, int ndim, int tx, int ty)
     OFM_FOR_TILES(X)
 #undef X
     return false;
+}
+
+int tile_list(int precision, int ndim, int (*out)[2], int cap)
+{
+    int k = 0;
+#define X(T, ND, TX, TY)                                                                        \
+    if ((precision == OFM_F64) == (sizeof(T) == 8) && ndim == ND) {                             \
+        if (k < cap) { out[k][0] = TX; out[k][1] = TY; }                                        \
+        ++k;                                                                                    \
+    }
+    OFM_FOR_TILES(X)
+#undef X
+    return k;
 }
 
 hipError_t launch_stage(int precision, int ndim, int tx, int ty, const LaunchArgs& a, int stage, hipStream_t s)

@@ -99,7 +99,7 @@ def test_fp64_ragged_tiles_and_chunks(ctx):
     cfg = solver_config("cloud50", 20)
     bub = sample_cloud(cloud_spec("cloud50"), MASTER_SEED, 0, 2)
     R, _ = OF.run_steps(cfg, OF.init_state(cfg, bub), 12)
-    for tune in [(16, 8, 16, 2), (8, 8, 7, 2), (16, 16, 32, 2)]:
+    for tune in [(16, 8, 16, 2), (8, 8, 7, 2), (16, 14, 32, 2)]:
         U, _, _ = gpu_run(ctx, cfg, "f64", bubbles=bub, n_steps=12, tune=tune)
         assert np.all(max_rel_field(oracle_shape(cfg, U), R) <= 1e-11), tune
 
@@ -112,11 +112,49 @@ def test_fp64_tiling_invariance_bitwise(ctx):
     cfg = solver_config("cloud50", 32)
     bub = sample_cloud(cloud_spec("cloud50"), MASTER_SEED, 0, 4)
     outs = [gpu_run(ctx, cfg, "f64", bubbles=bub, n_steps=6, tune=t)[0]
-            for t in [(16, 8, 16, 2), (8, 8, 32, 2), (16, 16, 5, 2), (16, 8, 1, 2)]]
+            for t in [(16, 8, 16, 2), (8, 8, 32, 2), (16, 14, 5, 2), (16, 8, 1, 2)]]
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
     again = gpu_run(ctx, cfg, "f64", bubbles=bub, n_steps=6, tune=(16, 8, 16, 2))[0]
     assert np.array_equal(again, outs[0])
+
+
+def test_fp32_tiling_invariance_bitwise(ctx):
+    """The same for the float kernels, on a grid (n = 40) that leaves ragged
+    tiles for every shape, including the tile whose workgroup has more
+    threads than cells (16 x 14)."""
+    say("fp32 tiling invariance")
+    cfg = solver_config("cloud50", 40)
+    bub = sample_cloud(cloud_spec("cloud50"), MASTER_SEED, 0, 5)
+    outs = [gpu_run(ctx, cfg, "f32", bubbles=bub, n_steps=5, tune=t)[0]
+            for t in [(16, 14, 16, 2), (16, 16, 7, 2), (16, 14, 40, 2), (16, 8, 3, 2)]]
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_autotune_times_every_candidate_and_keeps_the_fastest(ctx):
+    import torch
+    from paper_1705_04374_amd import capi
+    say("autotune")
+    cfg = solver_config("cloud50", 32)
+    bub = sample_cloud(cloud_spec("cloud50"), MASTER_SEED, 0, 6)
+    spec = capi.make_spec(cfg, "f32", n_steps=1)
+    st, bufs = alloc_state(cfg, "f32")
+    capi.ofm_state_init(ctx, spec, bub, st)
+    r = capi.ofm_autotune(ctx, spec, st, 1)
+    tab = r["table"]
+    tiles = sorted({(t[0], t[1]) for t in tab})
+    assert (16, 14) in tiles and len(tab) == len(tiles) * 3          # z-chunks 8, 16, 32 <= n
+    assert {t[2] for t in tab} == {8, 16, 32}
+    best = min(tab, key=lambda t: t[3])
+    assert (r["tx"], r["ty"], r["zchunk"]) == best[:3] and r["stage_ms_per_step"] == best[3]
+    assert all(t[3] > 0 for t in tab)
+    # the tuned entry is what later solves use, and it changes nothing in the result
+    tuned = gpu_run(ctx, cfg, "f32", bubbles=bub, n_steps=4)[0]
+    ref = gpu_run(ctx, cfg, "f32", bubbles=bub, n_steps=4, tune=(16, 14, 16, 2))[0]
+    assert np.array_equal(tuned, ref)
+    del bufs
+    torch.cuda.empty_cache()
 
 
 @pytest.mark.parametrize("case", ["sod", "water_air"])
