@@ -275,10 +275,12 @@ static int run(ofm_ctx* ctx, std::vector<Member>& mem, bool init, double* dts_ho
         HIPCHK(ctx, hipEventCreate(&kev[1]));
     }
     std::vector<double> live_cells(1, 0.0);
-    auto enqueue_steps = [&](int nsteps) -> int {
+    // g0: index of the first step enqueued (the state of step g sits in
+    // buffer g & 1; stage stg of step g reads buffer (3 g + stg) & 1)
+    auto enqueue_steps = [&](int nsteps, int64_t g0) -> int {
         for (int g = 0; g < nsteps; ++g)
             for (int stg = 0; stg < 3; ++stg) {
-                la.src = (g + stg) & 1;     // (3 g + stg) mod 2 with g counted from an even step
+                la.src = (int)((g0 + g + stg) & 1);
                 if (ctx->timing) HIPCHK(ctx, hipEventRecord(kev[0], stream));
                 HIPCHK(ctx, launch_stage(prec, nd, tc.tx, tc.ty, la, stg, stream));
                 if (ctx->timing) {
@@ -298,7 +300,7 @@ static int run(ofm_ctx* ctx, std::vector<Member>& mem, bool init, double* dts_ho
     hipGraphExec_t gexec = nullptr;
     if (!eager) {
         HIPCHK(ctx, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-        rc = enqueue_steps(K);
+        rc = enqueue_steps(K, 0);     // replayed at even step indices only
         hipError_t ce = hipStreamEndCapture(stream, &graph);
         if (rc) return rc;
         if (ce != hipSuccess) return fail(ctx, OFM_EHIP, "graph capture failed: %s", hipGetErrorString(ce));
@@ -309,13 +311,17 @@ static int run(ofm_ctx* ctx, std::vector<Member>& mem, bool init, double* dts_ho
     live_cells[0] = 0.0;
     for (int i = 0; i < ns; ++i) live_cells[0] += (double)cells_of(mem[i].spec);
     for (;;) {
-        if (eager) rc = enqueue_steps(K);
-        else {
+        int todo = K;
+        if (eager) {
+            // no launches past the step cap (they would find every sample done)
+            todo = (int)std::min<int64_t>(K, std::max<int64_t>(1, cap - taken));
+            rc = enqueue_steps(todo, taken);
+        } else {
             hipError_t le = hipGraphLaunch(gexec, stream);
             rc = le == hipSuccess ? OFM_OK : fail(ctx, OFM_EHIP, "graph launch failed: %s", hipGetErrorString(le));
         }
         if (rc) { result = rc; break; }
-        taken += K;
+        taken += todo;
         hipError_t ce = hipMemcpyAsync(ctx->host_state, d_state, sizeof(SampleState) * ns, hipMemcpyDeviceToHost, stream);
         if (ce == hipSuccess) ce = hipStreamSynchronize(stream);
         if (ce != hipSuccess) { result = fail(ctx, OFM_EHIP, "state read-back failed: %s", hipGetErrorString(ce)); break; }

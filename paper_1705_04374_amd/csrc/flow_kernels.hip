@@ -312,20 +312,22 @@ __device__ __forceinline__ void reduce_cell(const PhysD& ph, const T (&q)[4 + ND
 #pragma unroll
     for (int v = 0; v < NV; ++v) { qd[v] = (double)q[v]; finite = finite && isfinite(qd[v]); }
     double rho = qd[0] + qd[1];
+    const double irho = Num<double>::rcp(rho);
     double ke = 0.0, umax = 0.0;
 #pragma unroll
     for (int m = 0; m < ND; ++m) {
-        double u = qd[2 + m] / rho;
+        double u = qd[2 + m] * irho;
         ke += qd[2 + m] * u;
         umax = fmax(umax, fabs(u));
     }
     double a2 = qd[3 + ND];
     double G = ph.g1inv + a2 * (ph.g2inv - ph.g1inv);
     double P = ph.pi1 + a2 * (ph.pi2 - ph.pi1);
-    double p = (qd[2 + ND] - 0.5 * ke) / G;
+    const double iG = Num<double>::rcp(G);
+    double p = (qd[2 + ND] - 0.5 * ke) * iG;
     finite = finite && isfinite(p);
     if (!finite) { r.n_nf++; return; }
-    double c2 = ((G + 1.0) * p + P) / (G * rho);
+    double c2 = ((G + 1.0) * p + P) * iG * irho;
     if (!(rho > 0.0) || !(c2 > 0.0)) { r.n_c2++; return; }
     r.take(umax + sqrt(c2), p, idx);
 }
@@ -401,13 +403,14 @@ stage_kernel(LaunchArgs a, int stage)
     constexpr int NT = stage_threads<TX, TY>();
     constexpr int HX = TX + 6;
     constexpr int HY = ND >= 2 ? TY + 6 : 1;
-    // Task lists of the x-y phases.  The x block is padded to whole
-    // wavefronts so that no wavefront holds both x and y tasks (which would
-    // run both code paths under a split exec mask).
+    // Task lists of the x-y phases.  Edge tasks: x then y, contiguous (a
+    // wavefront may hold both; they differ only in the gather stride).  Face
+    // tasks: the x block is padded to whole wavefronts so that no wavefront
+    // holds both x and y faces (the two HLLC variants would both run under a
+    // split exec mask).
     constexpr int EXN = TY * (TX + 2);                         // x edge tasks
-    constexpr int EXP = ND >= 2 ? round_up64(EXN) : EXN;       // start of the y edge tasks
     constexpr int EYN = ND >= 2 ? (TY + 2) * TX : 0;           // y edge tasks
-    constexpr int ES = EXP + EYN;
+    constexpr int ES = EXN + EYN;
     constexpr int FXN = TY * (TX + 1);                         // x faces
     constexpr int FXP = ND >= 2 ? round_up64(FXN) : FXN;       // start of the y faces
     constexpr int FYN = ND >= 2 ? (TY + 1) * TX : 0;           // y faces
@@ -474,22 +477,18 @@ stage_kernel(LaunchArgs a, int stage)
     auto plane_xy = [&](T (&xy)[NV + 1]) {
         // edges along x of cells -1..TX of every row, along y of rows -1..TY
         for (int e = tid; e < ES; e += NT) {
-            if (e >= EXN && e < EXP) continue;             // padding of the x block
+            // stencil of five cells through the centre cell, `stride` apart in sW
+            const bool isx = e < EXN;
+            const int f = e - EXN;
+            const int row = e / (TX + 2), cx = e % (TX + 2) - 1;     // x task
+            const int cy = f / TX - 1, col = f % TX;                  // y task
+            const int base = isx ? (row + (ND >= 2 ? 3 : 0)) * HX + cx + 1 : (cy + 1) * HX + col + 3;
+            const int stride = isx ? 1 : HX;
             T s[5][NV], lo[NV], hi[NV];
-            if (e < EXP) {
-                const int row = e / (TX + 2), cx = e % (TX + 2) - 1;
 #pragma unroll
-                for (int k = 0; k < 5; ++k)
+            for (int k = 0; k < 5; ++k)
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) s[k][v] = sW[(v * HY + row + (ND >= 2 ? 3 : 0)) * HX + cx + 1 + k];
-            } else {
-                const int f = e - EXP;
-                const int cy = f / TX - 1, col = f % TX;
-#pragma unroll
-                for (int k = 0; k < 5; ++k)
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) s[k][v] = sW[(v * HY + cy + 1 + k) * HX + col + 3];
-            }
+                for (int v = 0; v < NV; ++v) s[k][v] = sW[v * HY * HX + base + k * stride];
             cell_edges<T, ND>(ph, s, lo, hi);
 #pragma unroll
             for (int v = 0; v < NV; ++v) { sEm[v * ES + e] = lo[v]; sEp[v * ES + e] = hi[v]; }
@@ -513,8 +512,8 @@ stage_kernel(LaunchArgs a, int stage)
                     const int j = g / TX, col = g % TX;
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
-                        wl[v] = sEp[v * ES + EXP + j * TX + col];
-                        wr[v] = sEm[v * ES + EXP + (j + 1) * TX + col];
+                        wl[v] = sEp[v * ES + EXN + j * TX + col];
+                        wr[v] = sEm[v * ES + EXN + (j + 1) * TX + col];
                     }
                     hllc<T, ND, 1 < ND ? 1 : 0>(ph, wl, wr, fl);
                 }
