@@ -534,23 +534,25 @@ stage_kernel(LaunchArgs a, int stage)
         }
     };
 
-    // finish one cell: L(U) from the flux-difference sums, then the stage
-    auto finish = [&](int64_t idx, const T (&sum)[NV + 1], const T (&wc)[NV]) {
-        T L[NV];
+    // L(U) of one cell from its flux-difference sums and primitives
+    auto rate = [&](const T (&sum)[NV + 1], const T (&wc)[NV], T (&L)[NV]) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) L[v] = sum[v] * ih;
         const T sk = wc[3 + ND] + k_coef<T>(ph, wc[3 + ND], wc[2 + ND]);
         const T divu = sum[NV] * ih;
         L[NV - 1] += sk * divu;              // R_7 = (a2 + K) div u
         L[NV - 2] -= ph.pinf(sk) * divu;     // Et = E - Pi(a2): -Pi(a2 + K) div u
+    };
+    // the low-storage RK stage of one cell, given its U and dU
+    auto update = [&](int64_t idx, const T (&L)[NV], const T (&uo)[NV], const T (&duo)[NV]) {
         T qn[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const int64_t o = v * ncell + idx;
             T dv = dt * L[v];
-            if (stage > 0) dv += rkA * du[o];
+            if (stage > 0) dv += rkA * duo[v];
             if (stage < 2) du[o] = dv;
-            qn[v] = ua[o] + rkB * dv;
+            qn[v] = uo[v] + rkB * dv;
             ub[o] = qn[v];
         }
         if (stage == 2) reduce_cell<T, ND>(a.ph, qn, idx, red);
@@ -564,7 +566,17 @@ stage_kernel(LaunchArgs a, int stage)
 #pragma unroll
         for (int v = 0; v < NV; ++v) wc[v] = sW[(v * HY + ty + (ND >= 2 ? 3 : 0)) * HX + tx + 3];
         plane_xy(xy);
-        if (mine) finish((ND == 2 ? (int64_t)gy * n : 0) + gx, xy, wc);
+        if (mine) {
+            const int64_t idx = (ND == 2 ? (int64_t)gy * n : 0) + gx;
+            T L[NV], uo[NV], duo[NV];
+            rate(xy, wc, L);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                uo[v] = ua[v * ncell + idx];
+                duo[v] = stage > 0 ? du[v * ncell + idx] : T(0);
+            }
+            update(idx, L, uo, duo);
+        }
     } else {
         const int z0 = tzc * a.zchunk;
         const int z1 = min(z0 + a.zchunk, n) - 1;      // last plane of the chunk
@@ -572,6 +584,12 @@ stage_kernel(LaunchArgs a, int stage)
         T pend[3][NV + 1];                             // x-y sums of planes p-3..p-1
         T ep_prev[NV];                                 // upper z edge of cell p-3
         T fz_lo[NV + 1];                               // lower z face of cell p-3
+        // A finished cell's update waits one plane: its U and dU loads are
+        // issued when its rate is known and consumed after the next plane's
+        // loads, so that the two memory latencies overlap.
+        bool upd = false;
+        int64_t uidx = 0;
+        T uL[NV], uo[NV], duo[NV];
 #pragma unroll
         for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -584,6 +602,7 @@ stage_kernel(LaunchArgs a, int stage)
             if (out) {
                 __syncthreads();
                 load_plane(p);
+                if (upd) { update(uidx, uL, uo, duo); upd = false; }
                 __syncthreads();
 #pragma unroll
                 for (int v = 0; v < NV; ++v) wn[v] = sW[(v * HY + ty + 3) * HX + tx + 3];
@@ -594,6 +613,7 @@ stage_kernel(LaunchArgs a, int stage)
 #pragma unroll
                 for (int v = 0; v < NV; ++v) qq[v] = ua[v * ncell + idx];
                 to_prim<T, ND>(ph, qq, wn);
+                if (upd) { update(uidx, uL, uo, duo); upd = false; }
 #pragma unroll
                 for (int v = 0; v <= NV; ++v) xy[v] = T(0);
             }
@@ -619,7 +639,16 @@ stage_kernel(LaunchArgs a, int stage)
                         T wc[NV];
 #pragma unroll
                         for (int v = 0; v < NV; ++v) wc[v] = q[1][v];
-                        finish((int64_t)(p - 3) * plane + (int64_t)gy * n + gx, sum, wc);
+                        rate(sum, wc, uL);
+                        uidx = (int64_t)(p - 3) * plane + (int64_t)gy * n + gx;
+                        // keep the loads here (not hoisted into the z-face work)
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) {
+                            uo[v] = ua[v * ncell + uidx];
+                            duo[v] = stage > 0 ? du[v * ncell + uidx] : T(0);
+                        }
+                        upd = true;
                     }
 #pragma unroll
                     for (int v = 0; v <= NV; ++v) fz_lo[v] = fz[v];
@@ -630,6 +659,7 @@ stage_kernel(LaunchArgs a, int stage)
 #pragma unroll
             for (int v = 0; v <= NV; ++v) { pend[0][v] = pend[1][v]; pend[1][v] = pend[2][v]; pend[2][v] = xy[v]; }
         }
+        if (upd) update(uidx, uL, uo, duo);
     }
     if (stage == 2) write_partial<NT>(red, a.part + d.tile0 + item.tile);
 }
