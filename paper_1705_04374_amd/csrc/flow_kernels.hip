@@ -13,10 +13,10 @@
 // the primitive variables of the tile plus a 3-cell halo in LDS, reconstructs
 // every cell along x and y (WENO5, both edges at once, with the cell-wise
 // positivity fallback), evaluates the HLLC face fluxes and the face
-// velocities, and keeps the x-y divergence of the plane in registers.  The z
-// direction uses a per-thread register queue of five planes, so each face is
-// computed once.  A plane's cells are finished three planes later, when their
-// upper z-face is known.
+// velocities, and sums the x-y flux differences of its cell.  The z direction
+// uses a per-thread register queue of the primitives of five planes of the
+// thread's own column, read three planes ahead, so that each z face is
+// computed once and a cell is finished in the iteration of its own plane.
 //
 // Layout in HBM: structure of arrays, one contiguous array per variable,
 // x fastest; three arrays per sample (two ping-pong state buffers and the
@@ -578,88 +578,71 @@ stage_kernel(LaunchArgs a, int stage)
             update(idx, L, uo, duo);
         }
     } else {
+        // z: each thread keeps the primitives of its own column, planes
+        // p-1..p+3, in registers (read from HBM three planes ahead of the
+        // x-y work), so that at plane p it knows the z edges of cell p+1 and
+        // finishes cell p in the same iteration.
         const int z0 = tzc * a.zchunk;
         const int z1 = min(z0 + a.zchunk, n) - 1;      // last plane of the chunk
-        T q[5][NV];                                    // primitives of planes p-4..p
-        T pend[3][NV + 1];                             // x-y sums of planes p-3..p-1
-        T ep_prev[NV];                                 // upper z edge of cell p-3
-        T fz_lo[NV + 1];                               // lower z face of cell p-3
-        // A finished cell's update waits one plane: its U and dU loads are
-        // issued when its rate is known and consumed after the next plane's
-        // loads, so that the two memory latencies overlap.
-        bool upd = false;
-        int64_t uidx = 0;
-        T uL[NV], uo[NV], duo[NV];
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-            for (int v = 0; v <= NV; ++v) pend[k][v] = T(0);
         const int cxg = min(gx, n - 1), cyg = min(gy, n - 1);
-        for (int p = z0 - 3; p <= z1 + 3; ++p) {
-            const bool out = p >= z0 && p <= z1;
-            T wn[NV];
+        const int64_t col = (int64_t)cyg * n + cxg;    // (clamped) column of this thread
+        T q[5][NV];                                    // primitives of planes p-1..p+3
+        T ep[NV];                                      // upper z edge of cell p
+        T fz_lo[NV + 1];                               // flux through face p-1/2
+        // One loop body does all the work (so that every edge and face is
+        // computed by the same code whatever the chunking, bit for bit):
+        // p = z0-6..z0-3 only fill the queue, p = z0-2 adds the edges of
+        // cell z0-1, p = z0-1 the face z0-1/2, and p >= z0 the x-y work of
+        // plane p and the update of cell p.
+        for (int p = z0 - 6; p <= z1; ++p) {
+            const bool xy_work = p >= z0;
+            // global loads issued before the x-y work: the column's plane
+            // p+3 and this cell's U and dU
+            const int64_t inext = (int64_t)bc_map(p + 3, n, bc) * plane + col;
+            const int64_t icell = (int64_t)p * plane + col;
+            T qn[NV], uo[NV], duo[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) qn[v] = ua[v * ncell + inext];
+            if (xy_work) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    uo[v] = ua[v * ncell + icell];
+                    duo[v] = stage > 0 ? du[v * ncell + icell] : T(0);
+                }
+            }
             T xy[NV + 1];
-            if (out) {
+            if (xy_work) {
                 __syncthreads();
                 load_plane(p);
-                if (upd) { update(uidx, uL, uo, duo); upd = false; }
                 __syncthreads();
-#pragma unroll
-                for (int v = 0; v < NV; ++v) wn[v] = sW[(v * HY + ty + 3) * HX + tx + 3];
                 plane_xy(xy);
-            } else {
-                const int64_t idx = (int64_t)bc_map(p, n, bc) * plane + (int64_t)cyg * n + cxg;
-                T qq[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) qq[v] = ua[v * ncell + idx];
-                to_prim<T, ND>(ph, qq, wn);
-                if (upd) { update(uidx, uL, uo, duo); upd = false; }
-#pragma unroll
-                for (int v = 0; v <= NV; ++v) xy[v] = T(0);
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k)
 #pragma unroll
                 for (int v = 0; v < NV; ++v) q[k][v] = q[k + 1][v];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) q[4][v] = wn[v];
-            if (p >= z0 + 1) {
-                // z edges of cell p-2
+            to_prim<T, ND>(ph, qn, q[4]);                          // planes p-1..p+3
+            if (p >= z0 - 2) {
                 T lo[NV], hi[NV];
-                cell_edges<T, ND>(ph, q, lo, hi);
-                if (p >= z0 + 2) {
-                    // face between p-3 and p-2
+                cell_edges<T, ND>(ph, q, lo, hi);                  // cell p+1
+                if (p >= z0 - 1) {
                     T fz[NV + 1];
-                    hllc<T, ND, ND - 1>(ph, ep_prev, lo, fz);
-                    if (p >= z0 + 3 && mine) {
-                        T sum[NV + 1];
+                    hllc<T, ND, ND - 1>(ph, ep, lo, fz);           // face p+1/2
+                    if (xy_work && mine) {
+                        T sum[NV + 1], L[NV];
 #pragma unroll
-                        for (int v = 0; v < NV; ++v) sum[v] = pend[0][v] + (fz_lo[v] - fz[v]);
-                        sum[NV] = pend[0][NV] + (fz[NV] - fz_lo[NV]);
-                        T wc[NV];
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) wc[v] = q[1][v];
-                        rate(sum, wc, uL);
-                        uidx = (int64_t)(p - 3) * plane + (int64_t)gy * n + gx;
-                        // keep the loads here (not hoisted into the z-face work)
-                        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) {
-                            uo[v] = ua[v * ncell + uidx];
-                            duo[v] = stage > 0 ? du[v * ncell + uidx] : T(0);
-                        }
-                        upd = true;
+                        for (int v = 0; v < NV; ++v) sum[v] = xy[v] + (fz_lo[v] - fz[v]);
+                        sum[NV] = xy[NV] + (fz[NV] - fz_lo[NV]);
+                        rate(sum, q[1], L);
+                        update(icell, L, uo, duo);
                     }
 #pragma unroll
                     for (int v = 0; v <= NV; ++v) fz_lo[v] = fz[v];
                 }
 #pragma unroll
-                for (int v = 0; v < NV; ++v) ep_prev[v] = hi[v];
+                for (int v = 0; v < NV; ++v) ep[v] = hi[v];
             }
-#pragma unroll
-            for (int v = 0; v <= NV; ++v) { pend[0][v] = pend[1][v]; pend[1][v] = pend[2][v]; pend[2][v] = xy[v]; }
         }
-        if (upd) update(uidx, uL, uo, duo);
     }
     if (stage == 2) write_partial<NT>(red, a.part + d.tile0 + item.tile);
 }
