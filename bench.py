@@ -48,6 +48,32 @@ WORDS_PER_CELL_STEP = 10 * 7
 FLOPS_PER_CELL_STAGE = 2650
 
 
+PROFILE = os.path.join(ROOT, "profiles", "stage_kernel_cloud500_256cubed_f32.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1705_04374_amd", "csrc", "flow_kernels.hip")
+
+
+def profiled_traffic(tile, n, precision):
+    """HBM bytes per stage launch measured with rocprofv3 (FETCH_SIZE and
+    WRITE_SIZE, scaled by a plain copy's counts), as recorded in the profile
+    summary; None unless that summary is for the kernel source, tile and
+    workload measured here."""
+    import hashlib
+    if precision != "f32" or n != 256 or tile is None or not os.path.exists(PROFILE):
+        return None
+    fields = {}
+    with open(PROFILE) as f:
+        for line in f:
+            k, _, v = line.strip().partition(": ")
+            if v:
+                fields[k] = v.strip()
+    with open(KERNEL_SOURCE, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    want = "%dx%dx%d" % (tile["tx"], tile["ty"], tile["zchunk"])
+    if not sha.startswith(fields.get("kernel_source_sha256_prefix", "-")) or fields.get("tile") != want:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +200,9 @@ def main():
     hbm_frac = gbs / HBM_PEAK_GBS
     alu_frac = tfl / VALU_PEAK_TFLOPS[a.precision]
     bound = "alu" if alu_frac >= hbm_frac else "hbm"
+    used = capi.ofm_tune_get(ctx, capi.OFM_F32 if a.precision == "f32" else capi.OFM_F64, 3, n)
+    tile = {k: used[k] for k in ("tx", "ty", "zchunk")}
+    traffic = profiled_traffic(tile, n, a.precision)
     roof = {
         "kernel": "stage_kernel (fused WENO5/HLLC RHS + LSRK3 stage, 3 launches per step)",
         "bound": bound,
@@ -181,9 +210,10 @@ def main():
         "peak": VALU_PEAK_TFLOPS[a.precision] if bound == "alu" else HBM_PEAK_GBS,
         "unit": "TFLOP/s" if bound == "alu" else "GB/s",
         "frac": round(alu_frac if bound == "alu" else hbm_frac, 4),
-        "traffic": None,
+        "traffic": traffic,
+        "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
         "avg_launch_ms": round(avg_ms, 4),
-        "tile": None if r["tuned"] is None else {k: r["tuned"][k] for k in ("tx", "ty", "zchunk")},
+        "tile": tile,
         "hbm": {"achieved_GBs": round(gbs, 1), "peak_GBs": HBM_PEAK_GBS, "frac": round(hbm_frac, 4),
                 "algorithmic_bytes_per_launch": bytes_per_launch},
         "alu": {"achieved_TFLOPs": round(tfl, 2), "peak_TFLOPs": VALU_PEAK_TFLOPS[a.precision],

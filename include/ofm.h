@@ -240,6 +240,11 @@ typedef struct ofm_tune_result {
     int32_t reserved;
 } ofm_tune_result;
 
+/* The tile and schedule that solves of (precision, ndim, n) use now (the
+ * default, or the entry ofm_tune_set / ofm_autotune stored); out [host]
+ * receives tx, ty, zchunk, graph_steps (stage_ms_per_step 0, candidates 0). */
+int ofm_tune_get(const ofm_ctx* ctx, int32_t precision, int32_t ndim, int32_t n, ofm_tune_result* out);
+
 /* Measure every compiled tile shape (and, in 3-D, z-chunks of 8, 16, 32 and
  * 64 planes not larger than n) of the stage kernel for spec's precision,
  * dimension and grid, by stepping the caller's state st [dev] `steps` time

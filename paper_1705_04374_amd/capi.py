@@ -27,7 +27,7 @@ EXPORTS = [
     "ofm_ctx_create", "ofm_ctx_destroy", "ofm_last_error", "ofm_sample_cloud", "ofm_state_init",
     "ofm_state_from_primitive", "ofm_state_to_conserved", "ofm_step", "ofm_solve", "ofm_solve_batch", "ofm_last_solve_stats",
     "ofm_mlmc_moments", "ofm_ofmlmc_coefficients", "ofm_ofmlmc_errors", "ofm_ofmlmc_estimate",
-    "ofm_ofmlmc_optimal_M", "ofm_tune_set", "ofm_autotune", "ofm_kernel_timing", "ofm_kernel_times",
+    "ofm_ofmlmc_optimal_M", "ofm_tune_set", "ofm_tune_get", "ofm_autotune", "ofm_kernel_timing", "ofm_kernel_times",
     "ofm_nn_create", "ofm_nn_destroy", "ofm_nn_param_count", "ofm_nn_get_params", "ofm_nn_set_params",
     "ofm_nn_set_normalization", "ofm_nn_reset_optimizer", "ofm_nn_features", "ofm_nn_forward", "ofm_nn_grads",
     "ofm_nn_train_step",
@@ -128,6 +128,7 @@ def lib():
         L.ofm_ofmlmc_estimate.argtypes = [vp, i32, vp, vp, vp, vp]
         L.ofm_ofmlmc_optimal_M.argtypes = [vp, i32, vp, vp, vp, i32, C.c_double, vp, vp, vp]
         L.ofm_tune_set.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32]
+        L.ofm_tune_get.argtypes = [vp, i32, i32, i32, C.POINTER(TuneResult)]
         L.ofm_autotune.argtypes = [vp, C.POINTER(SolveSpec), C.POINTER(StateView), i32, C.POINTER(TuneResult),
                                    C.POINTER(TuneResult), i32, vp]
         L.ofm_kernel_timing.argtypes = [vp, i32]
@@ -322,6 +323,12 @@ def ofm_ofmlmc_optimal_M(ctx: Context, L: int, sig, W, have, mode: int, target: 
 def ofm_tune_set(ctx: Context, precision: int, ndim: int, n: int, tx: int, ty: int, zchunk: int,
                  graph_steps: int):
     ctx.check(lib().ofm_tune_set(ctx.h, precision, ndim, n, tx, ty, zchunk, graph_steps))
+
+
+def ofm_tune_get(ctx: Context, precision: int, ndim: int, n: int) -> dict:
+    r = TuneResult()
+    ctx.check(lib().ofm_tune_get(ctx.h, precision, ndim, n, C.byref(r)))
+    return dict(tx=r.tx, ty=r.ty, zchunk=r.zchunk, graph_steps=r.graph_steps)
 
 
 def ofm_autotune(ctx: Context, spec: SolveSpec, st: StateView, steps: int = 2, stream=None) -> dict:

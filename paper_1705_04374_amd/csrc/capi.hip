@@ -568,6 +568,16 @@ int ofm_tune_set(ofm_ctx* ctx, int32_t precision, int32_t ndim, int32_t n, int32
     return OFM_OK;
 }
 
+int ofm_tune_get(const ofm_ctx* ctx, int32_t precision, int32_t ndim, int32_t n, ofm_tune_result* out)
+{
+    if (!ctx || !out) return fail(nullptr, OFM_EINVAL, "ofm_tune_get: null argument");
+    if (ndim < 1 || ndim > 3 || (precision != OFM_F32 && precision != OFM_F64) || n < 1)
+        return fail(const_cast<ofm_ctx*>(ctx), OFM_EINVAL, "ofm_tune_get: bad precision, ndim or n");
+    const TileChoice t = ctx->tuning.choose(precision, ndim, n, 1);
+    *out = ofm_tune_result{ t.tx, t.ty, t.zchunk, t.graph_steps, 0.0, 0, 0 };
+    return OFM_OK;
+}
+
 int ofm_autotune(ofm_ctx* ctx, const ofm_solve_spec* spec, ofm_state_view* st, int32_t steps,
                  ofm_tune_result* out, ofm_tune_result* all, int32_t all_cap, void* stream)
 {
