@@ -217,6 +217,32 @@ int ofm_solve(ofm_ctx* ctx, const ofm_solve_spec* spec, const double* bubbles,
 int ofm_solve_batch(ofm_ctx* ctx, const ofm_batch_item* items, int32_t n, ofm_qoi* qoi,
                     void* stream);
 
+/* ---- long batched runs, advanced in portions ---------------------------- */
+
+/* A batched solve kept on the device between calls, so that a long run can
+ * report progress, be time-sliced or interleaved with other work.  The same
+ * solve as ofm_solve_batch (same kernels, same QoIs).
+ *
+ * ofm_run_begin: validates the n items [host] as ofm_solve_batch does,
+ *   allocates the run's own state arrays (3 arrays of (4 + ndim) n^ndim
+ *   values per item; OFM_ENOMEM if they do not fit), builds Q_0 of every item
+ *   from its bubbles, takes the initial reduction and captures the step graph.
+ *   The bubbles are copied; the caller may free them on return.  Waits for
+ *   work queued on `stream` first; synchronous.
+ * ofm_run_advance: advances until every sample is done or at least max_steps
+ *   (>= 1) more time steps have been taken (whole graphs of steps); *done
+ *   [host, may be NULL] = 1 once every sample is done.  Synchronous.
+ * ofm_run_status: per item QoIs so far [host, n entries, may be NULL] (status
+ *   OK with t < t_end while a sample is still running), steps taken by the
+ *   run, seconds of initialisation and of stepping so far.
+ * ofm_run_destroy: frees the run (NULL is ignored).
+ * A run uses the context's stream; it must not outlive its context. */
+typedef struct ofm_run ofm_run;
+int ofm_run_begin(ofm_ctx* ctx, const ofm_batch_item* items, int32_t n, ofm_run** out, void* stream);
+int ofm_run_advance(ofm_run* run, int64_t max_steps, int32_t* done);
+int ofm_run_status(const ofm_run* run, ofm_qoi* qoi, int64_t* steps_taken, double* init_s, double* step_s);
+void ofm_run_destroy(ofm_run* run);
+
 /* Time spent in the last ofm_solve/ofm_solve_batch, in seconds, split into
  * initialisation and time stepping, and the number of cell-steps advanced. */
 int ofm_last_solve_stats(const ofm_ctx* ctx, double* init_s, double* step_s,

@@ -25,7 +25,8 @@ SAMPLE_OK, SAMPLE_NONFINITE, SAMPLE_NEGATIVE_C2, SAMPLE_MAX_STEPS = 0, 1, 2, 3
 # Every symbol include/ofm.h declares.
 EXPORTS = [
     "ofm_ctx_create", "ofm_ctx_destroy", "ofm_last_error", "ofm_sample_cloud", "ofm_state_init",
-    "ofm_state_from_primitive", "ofm_state_to_conserved", "ofm_step", "ofm_solve", "ofm_solve_batch", "ofm_last_solve_stats",
+    "ofm_state_from_primitive", "ofm_state_to_conserved", "ofm_step", "ofm_solve", "ofm_solve_batch", "ofm_run_begin", "ofm_run_advance", "ofm_run_status", "ofm_run_destroy",
+    "ofm_last_solve_stats",
     "ofm_mlmc_moments", "ofm_ofmlmc_coefficients", "ofm_ofmlmc_errors", "ofm_ofmlmc_estimate",
     "ofm_ofmlmc_optimal_M", "ofm_tune_set", "ofm_tune_get", "ofm_autotune", "ofm_kernel_timing", "ofm_kernel_times",
     "ofm_nn_create", "ofm_nn_destroy", "ofm_nn_param_count", "ofm_nn_get_params", "ofm_nn_set_params",
@@ -122,6 +123,11 @@ def lib():
         L.ofm_solve.argtypes = [vp, C.POINTER(SolveSpec), dp, i32, C.POINTER(Qoi), vp]
         L.ofm_solve_batch.argtypes = [vp, C.POINTER(BatchItem), i32, C.POINTER(Qoi), vp]
         L.ofm_last_solve_stats.argtypes = [vp, dp, dp, dp]
+        L.ofm_run_begin.argtypes = [vp, C.POINTER(BatchItem), i32, C.POINTER(vp), vp]
+        L.ofm_run_advance.argtypes = [vp, i64, C.POINTER(i32)]
+        L.ofm_run_status.argtypes = [vp, C.POINTER(Qoi), C.POINTER(i64), dp, dp]
+        L.ofm_run_destroy.argtypes = [vp]
+        L.ofm_run_destroy.restype = None
         L.ofm_mlmc_moments.argtypes = [vp, vp, vp, vp, i64, vp, vp]
         L.ofm_ofmlmc_coefficients.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.ofm_ofmlmc_errors.argtypes = [vp, i32, vp, vp, vp, vp, vp]
@@ -288,6 +294,48 @@ def ofm_solve_batch(ctx: Context, specs, bubbles_list, stream=None) -> list:
     qs = (Qoi * n)()
     ctx.check(lib().ofm_solve_batch(ctx.h, items, n, qs, _stream(stream)))
     return [q.as_dict() for q in qs]
+
+
+class Run:
+    """A batched solve kept on the device and advanced in portions
+    (ofm_run_* calls): the same solve as ofm_solve_batch."""
+
+    def __init__(self, ctx: Context, specs, bubbles_list, stream=None):
+        n = len(specs)
+        items = (BatchItem * n)()
+        keep = []
+        for i, (s, bl) in enumerate(zip(specs, bubbles_list)):
+            b, p, nb = _bub(bl)
+            keep.append((s, b))
+            items[i].spec = C.pointer(s)
+            items[i].bubbles = p
+            items[i].n_bubbles = nb
+        self.ctx, self.n = ctx, n
+        self.h = C.c_void_p()
+        ctx.check(lib().ofm_run_begin(ctx.h, items, n, C.byref(self.h), _stream(stream)))
+
+    def advance(self, max_steps: int) -> bool:
+        """Advance by at least max_steps steps (or to the end); True once done."""
+        done = C.c_int32()
+        self.ctx.check(lib().ofm_run_advance(self.h, max_steps, C.byref(done)))
+        return bool(done.value)
+
+    def status(self) -> dict:
+        qs = (Qoi * self.n)()
+        steps, a, b = C.c_int64(), C.c_double(), C.c_double()
+        self.ctx.check(lib().ofm_run_status(self.h, qs, C.byref(steps), C.byref(a), C.byref(b)))
+        return dict(qoi=[q.as_dict() for q in qs], steps=steps.value, init_s=a.value, step_s=b.value)
+
+    def close(self):
+        if self.h:
+            lib().ofm_run_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def ofm_last_solve_stats(ctx: Context) -> dict:

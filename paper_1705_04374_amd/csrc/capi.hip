@@ -126,22 +126,79 @@ struct Member {
     ofm_solve_spec spec;
     const double* bubbles;  // host
     int32_t nb;
-    void* buf0; void* buf1; void* du;   // device arrays (caller's or arena)
+    void* buf0; void* buf1; void* du;   // device arrays (caller's, the context's arena or the run's)
 };
 
-struct RunOut {
-    std::vector<SampleState> state;
-    std::vector<SampleDesc> desc;
+}  // namespace ofm
+
+// A batched run in progress: the members, their device descriptors and
+// sample states, the captured graph of K steps and the step count.  The
+// synchronous entry points build one, advance it to the end and drop it; an
+// ofm_run handle keeps it between calls.  Device metadata and the pinned
+// host mirror are the run's own when `own` is set (handles), else the
+// context's cached buffers.
+struct ofm_run {
+    ofm_ctx* ctx = nullptr;
+    bool own = false;
+    std::vector<ofm::Member> mem;
+    std::vector<ofm::SampleDesc> desc;
+    std::vector<ofm::SampleState> state;   // host copy after the last advance
+    ofm::TileChoice tc{};
+    ofm::LaunchArgs la{};
+    void* meta = nullptr;                   // own metadata (when own)
+    ofm::SampleState* pinned = nullptr;     // own pinned mirror (when own)
+    ofm::SampleState* host_state = nullptr;
+    ofm::SampleState* d_state = nullptr;
+    ofm::SampleDesc* d_desc = nullptr;
+    ofm::TilePartial* d_part = nullptr;
+    double* d_dt = nullptr;
+    int64_t dts_len = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipEvent_t kev[2] = { nullptr, nullptr };
+    bool eager = false;
+    int K = 2;
+    int64_t taken = 0, cap = 0;
+    double live_cells = 0.0;
+    double init_s = 0.0, step_s = 0.0;
+    void* arena = nullptr;                  // state arrays owned by a handle
+    bool finished = false;
+
+    ~ofm_run()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (hipEvent_t e : kev)
+            if (e) (void)hipEventDestroy(e);
+        if (own) {
+            if (meta) (void)hipFree(meta);
+            if (pinned) (void)hipHostFree(pinned);
+            if (arena) (void)hipFree(arena);
+        }
+    }
 };
 
-// Runs members to completion.  init: 1 = build Q_0 from bubbles, 0 = use buf0.
-static int run(ofm_ctx* ctx, std::vector<Member>& mem, bool init, double* dts_host, int64_t dts_len,
-               RunOut& ro, hipStream_t user_stream)
+namespace ofm {
+
+static double elapsed_s(hipEvent_t a, hipEvent_t b)
+{
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    return ms * 1e-3;
+}
+
+// Set up a run of r.mem: descriptors, work list, (init: Q_0 from the
+// bubbles, else buf0 as given), the initial reduction and the step graph.
+// dts_len > 0 records the step sizes on the device (eager launches).
+static int run_begin(ofm_ctx* ctx, ofm_run& r, bool init, int64_t dts_len, hipStream_t user_stream)
 {
     // Work already queued by the caller comes first; the solve itself runs on
     // the context's own non-blocking stream, which graph capture requires.
     HIPCHK(ctx, hipStreamSynchronize(user_stream));
     hipStream_t stream = ctx->stream;
+    std::vector<Member>& mem = r.mem;
+    r.ctx = ctx;
+    r.dts_len = dts_len;
     const int ns = (int)mem.size();
     const ofm_solve_spec& s0 = mem[0].spec;
     const int prec = s0.precision, nd = s0.ndim, bc = s0.bc;
@@ -154,11 +211,12 @@ static int run(ofm_ctx* ctx, std::vector<Member>& mem, bool init, double* dts_ho
     // tiling
     int maxn = 0;
     for (const Member& m : mem) maxn = std::max(maxn, m.spec.n);
-    const TileChoice tc = ctx->tuning.choose(prec, nd, maxn, ns);
-    ro.desc.assign(ns, SampleDesc{});
+    r.tc = ctx->tuning.choose(prec, nd, maxn, ns);
+    const TileChoice& tc = r.tc;
+    r.desc.assign(ns, SampleDesc{});
     int tiles = 0;
     for (int i = 0; i < ns; ++i) {
-        SampleDesc& d = ro.desc[i];
+        SampleDesc& d = r.desc[i];
         const ofm_solve_spec& s = mem[i].spec;
         d.buf[0] = mem[i].buf0;
         d.buf[1] = mem[i].buf1;
@@ -183,7 +241,7 @@ static int run(ofm_ctx* ctx, std::vector<Member>& mem, bool init, double* dts_ho
     std::vector<WorkItem> work;
     work.reserve(tiles);
     for (int i : order)
-        for (int t = 0; t < ro.desc[i].ntiles; ++t) work.push_back(WorkItem{ i, t });
+        for (int t = 0; t < r.desc[i].ntiles; ++t) work.push_back(WorkItem{ i, t });
 
     const size_t o_desc = 0;
     const size_t o_state = align256(o_desc + sizeof(SampleDesc) * ns);
@@ -191,32 +249,47 @@ static int run(ofm_ctx* ctx, std::vector<Member>& mem, bool init, double* dts_ho
     const size_t o_work = align256(o_part + sizeof(TilePartial) * tiles);
     const size_t o_dt = align256(o_work + sizeof(WorkItem) * work.size());
     const size_t meta_need = o_dt + sizeof(double) * (size_t)std::max<int64_t>(dts_len, 1);
-    int rc = grow(ctx, &ctx->meta, &ctx->meta_bytes, meta_need);
-    if (rc) return rc;
-    char* meta = (char*)ctx->meta;
-    SampleDesc* d_desc = (SampleDesc*)(meta + o_desc);
-    SampleState* d_state = (SampleState*)(meta + o_state);
-    TilePartial* d_part = (TilePartial*)(meta + o_part);
+    char* meta;
+    if (r.own) {
+        HIPCHK(ctx, hipMalloc(&r.meta, meta_need));
+        HIPCHK(ctx, hipHostMalloc((void**)&r.pinned, sizeof(SampleState) * ns, hipHostMallocDefault));
+        meta = (char*)r.meta;
+        r.host_state = r.pinned;
+    } else {
+        int rc = grow(ctx, &ctx->meta, &ctx->meta_bytes, meta_need);
+        if (rc) return rc;
+        if (ctx->host_state_cap < (size_t)ns) {
+            if (ctx->host_state) (void)hipHostFree(ctx->host_state);
+            ctx->host_state = nullptr;
+            ctx->host_state_cap = 0;
+            HIPCHK(ctx, hipHostMalloc((void**)&ctx->host_state, sizeof(SampleState) * ns, hipHostMallocDefault));
+            ctx->host_state_cap = ns;
+        }
+        meta = (char*)ctx->meta;
+        r.host_state = ctx->host_state;
+    }
+    r.d_desc = (SampleDesc*)(meta + o_desc);
+    r.d_state = (SampleState*)(meta + o_state);
+    r.d_part = (TilePartial*)(meta + o_part);
     WorkItem* d_work = (WorkItem*)(meta + o_work);
-    double* d_dt = dts_host ? (double*)(meta + o_dt) : nullptr;
+    r.d_dt = dts_len > 0 ? (double*)(meta + o_dt) : nullptr;
 
     std::vector<SampleState> st0(ns);
     for (auto& s : st0) memset(&s, 0, sizeof s);
-    HIPCHK(ctx, hipMemcpyAsync(d_desc, ro.desc.data(), sizeof(SampleDesc) * ns, hipMemcpyHostToDevice, stream));
-    HIPCHK(ctx, hipMemcpyAsync(d_state, st0.data(), sizeof(SampleState) * ns, hipMemcpyHostToDevice, stream));
+    HIPCHK(ctx, hipMemcpyAsync(r.d_desc, r.desc.data(), sizeof(SampleDesc) * ns, hipMemcpyHostToDevice, stream));
+    HIPCHK(ctx, hipMemcpyAsync(r.d_state, st0.data(), sizeof(SampleState) * ns, hipMemcpyHostToDevice, stream));
     HIPCHK(ctx, hipMemcpyAsync(d_work, work.data(), sizeof(WorkItem) * work.size(), hipMemcpyHostToDevice, stream));
 
-    hipEvent_t e0, e1, e2;
+    hipEvent_t e0, e1;
     HIPCHK(ctx, hipEventCreate(&e0));
     HIPCHK(ctx, hipEventCreate(&e1));
-    HIPCHK(ctx, hipEventCreate(&e2));
     HIPCHK(ctx, hipEventRecord(e0, stream));
 
     const PhysD ph = make_phys(s0);
     if (init) {
         size_t nbub = 0;
         for (const Member& m : mem) nbub += (size_t)m.nb;
-        rc = grow(ctx, &ctx->bub, &ctx->bub_bytes, sizeof(double) * 4 * std::max<size_t>(nbub, 1));
+        int rc = grow(ctx, &ctx->bub, &ctx->bub_bytes, sizeof(double) * 4 * std::max<size_t>(nbub, 1));
         if (rc) return rc;
         std::vector<double> hb;
         hb.reserve(4 * nbub);
@@ -242,120 +315,158 @@ static int run(ofm_ctx* ctx, std::vector<Member>& mem, bool init, double* dts_ho
         // the host bubbles vector must outlive the copy
         HIPCHK(ctx, hipStreamSynchronize(stream));
     }
-    LaunchArgs la;
+    LaunchArgs& la = r.la;
     la.ph = ph;
     la.work = d_work;
     la.n_work = (int)work.size();
     la.zchunk = tc.zchunk;
-    la.desc = d_desc;
-    la.state = d_state;
-    la.part = d_part;
+    la.desc = r.d_desc;
+    la.state = r.d_state;
+    la.part = r.d_part;
     la.bc = bc;
     la.src = 0;
     HIPCHK(ctx, launch_reduce(prec, nd, tc.tx, tc.ty, la, stream));
-    HIPCHK(ctx, launch_finalize(d_desc, d_state, d_part, ns, 1, d_dt, dts_len, stream));
+    HIPCHK(ctx, launch_finalize(r.d_desc, r.d_state, r.d_part, ns, 1, r.d_dt, dts_len, stream));
     HIPCHK(ctx, hipEventRecord(e1, stream));
+    HIPCHK(ctx, hipEventSynchronize(e1));
+    r.init_s = elapsed_s(e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
 
-    // time stepping: graphs of K steps replayed until every sample is done
-    if (ctx->host_state_cap < (size_t)ns) {
-        if (ctx->host_state) (void)hipHostFree(ctx->host_state);
-        ctx->host_state = nullptr;
-        HIPCHK(ctx, hipHostMalloc((void**)&ctx->host_state, sizeof(SampleState) * ns, hipHostMallocDefault));
-        ctx->host_state_cap = ns;
-    }
-    int64_t cap = 0;
-    for (const Member& m : mem) cap = std::max(cap, m.spec.n_steps > 0 ? m.spec.n_steps : m.spec.max_steps);
+    r.cap = 0;
+    for (const Member& m : mem) r.cap = std::max(r.cap, m.spec.n_steps > 0 ? m.spec.n_steps : m.spec.max_steps);
     // eager launches for the low-level stepper (per-step control) and while
     // kernels are being timed; captured graphs otherwise
-    const bool eager = dts_host != nullptr || ctx->timing;
-    const int K = eager ? 2 : tc.graph_steps;
-    hipEvent_t kev[2] = { nullptr, nullptr };
+    r.eager = dts_len > 0 || ctx->timing;
+    r.K = r.eager ? 2 : tc.graph_steps;
     if (ctx->timing) {
-        HIPCHK(ctx, hipEventCreate(&kev[0]));
-        HIPCHK(ctx, hipEventCreate(&kev[1]));
+        HIPCHK(ctx, hipEventCreate(&r.kev[0]));
+        HIPCHK(ctx, hipEventCreate(&r.kev[1]));
     }
-    std::vector<double> live_cells(1, 0.0);
-    // g0: index of the first step enqueued (the state of step g sits in
-    // buffer g & 1; stage stg of step g reads buffer (3 g + stg) & 1)
-    auto enqueue_steps = [&](int nsteps, int64_t g0) -> int {
-        for (int g = 0; g < nsteps; ++g)
-            for (int stg = 0; stg < 3; ++stg) {
-                la.src = (int)((g0 + g + stg) & 1);
-                if (ctx->timing) HIPCHK(ctx, hipEventRecord(kev[0], stream));
-                HIPCHK(ctx, launch_stage(prec, nd, tc.tx, tc.ty, la, stg, stream));
-                if (ctx->timing) {
-                    HIPCHK(ctx, hipEventRecord(kev[1], stream));
-                    HIPCHK(ctx, hipEventSynchronize(kev[1]));
-                    float ms = 0.f;
-                    HIPCHK(ctx, hipEventElapsedTime(&ms, kev[0], kev[1]));
-                    ctx->t_launches += 1;
-                    ctx->t_ms += ms;
-                    ctx->t_cells += live_cells[0];
-                }
-                if (stg == 2) HIPCHK(ctx, launch_finalize(d_desc, d_state, d_part, ns, 0, d_dt, dts_len, stream));
-            }
-        return OFM_OK;
-    };
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    if (!eager) {
+    r.live_cells = 0.0;
+    for (int i = 0; i < ns; ++i) r.live_cells += (double)cells_of(mem[i].spec);
+    r.state.assign(st0.begin(), st0.end());
+    if (!r.eager) {
         HIPCHK(ctx, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-        rc = enqueue_steps(K, 0);     // replayed at even step indices only
-        hipError_t ce = hipStreamEndCapture(stream, &graph);
+        int rc = OFM_OK;
+        for (int g = 0; g < r.K && rc == OFM_OK; ++g)
+            for (int stg = 0; stg < 3 && rc == OFM_OK; ++stg) {
+                la.src = (g + stg) & 1;     // replayed at even step indices only
+                hipError_t le = launch_stage(prec, nd, tc.tx, tc.ty, la, stg, stream);
+                if (le == hipSuccess && stg == 2)
+                    le = launch_finalize(r.d_desc, r.d_state, r.d_part, ns, 0, r.d_dt, dts_len, stream);
+                if (le != hipSuccess) rc = fail(ctx, OFM_EHIP, "launch failed: %s", hipGetErrorString(le));
+            }
+        hipError_t ce = hipStreamEndCapture(stream, &r.graph);
         if (rc) return rc;
         if (ce != hipSuccess) return fail(ctx, OFM_EHIP, "graph capture failed: %s", hipGetErrorString(ce));
-        HIPCHK(ctx, hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+        HIPCHK(ctx, hipGraphInstantiate(&r.gexec, r.graph, nullptr, nullptr, 0));
     }
-    int64_t taken = 0;
+    return OFM_OK;
+}
+
+// Eager launches of steps g0 .. g0+nsteps-1 (the state of step g sits in
+// buffer g & 1; stage stg of step g reads buffer (3 g + stg) & 1).
+static int run_enqueue(ofm_run& r, int nsteps, int64_t g0)
+{
+    ofm_ctx* ctx = r.ctx;
+    hipStream_t stream = ctx->stream;
+    const ofm_solve_spec& s0 = r.mem[0].spec;
+    const int ns = (int)r.mem.size();
+    for (int g = 0; g < nsteps; ++g)
+        for (int stg = 0; stg < 3; ++stg) {
+            r.la.src = (int)((g0 + g + stg) & 1);
+            if (ctx->timing) HIPCHK(ctx, hipEventRecord(r.kev[0], stream));
+            HIPCHK(ctx, launch_stage(s0.precision, s0.ndim, r.tc.tx, r.tc.ty, r.la, stg, stream));
+            if (ctx->timing) {
+                HIPCHK(ctx, hipEventRecord(r.kev[1], stream));
+                HIPCHK(ctx, hipEventSynchronize(r.kev[1]));
+                float ms = 0.f;
+                HIPCHK(ctx, hipEventElapsedTime(&ms, r.kev[0], r.kev[1]));
+                ctx->t_launches += 1;
+                ctx->t_ms += ms;
+                ctx->t_cells += r.live_cells;
+            }
+            if (stg == 2)
+                HIPCHK(ctx, launch_finalize(r.d_desc, r.d_state, r.d_part, ns, 0, r.d_dt, r.dts_len, stream));
+        }
+    return OFM_OK;
+}
+
+// Advance until every sample is done or at least max_steps more steps have
+// been enqueued (whole graphs of K steps); r.state holds the states after.
+static int run_advance(ofm_run& r, int64_t max_steps)
+{
+    ofm_ctx* ctx = r.ctx;
+    hipStream_t stream = ctx->stream;
+    const int ns = (int)r.mem.size();
+    if (r.finished) return OFM_OK;
+    hipEvent_t e0, e1;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    HIPCHK(ctx, hipEventRecord(e0, stream));
+    const int64_t start = r.taken;
     int result = OFM_OK;
-    live_cells[0] = 0.0;
-    for (int i = 0; i < ns; ++i) live_cells[0] += (double)cells_of(mem[i].spec);
     for (;;) {
-        int todo = K;
-        if (eager) {
+        int todo = r.K;
+        int rc;
+        if (r.eager) {
             // no launches past the step cap (they would find every sample done)
-            todo = (int)std::min<int64_t>(K, std::max<int64_t>(1, cap - taken));
-            rc = enqueue_steps(todo, taken);
+            todo = (int)std::min<int64_t>(r.K, std::max<int64_t>(1, r.cap - r.taken));
+            rc = run_enqueue(r, todo, r.taken);
         } else {
-            hipError_t le = hipGraphLaunch(gexec, stream);
+            hipError_t le = hipGraphLaunch(r.gexec, stream);
             rc = le == hipSuccess ? OFM_OK : fail(ctx, OFM_EHIP, "graph launch failed: %s", hipGetErrorString(le));
         }
         if (rc) { result = rc; break; }
-        taken += todo;
-        hipError_t ce = hipMemcpyAsync(ctx->host_state, d_state, sizeof(SampleState) * ns, hipMemcpyDeviceToHost, stream);
+        r.taken += todo;
+        hipError_t ce = hipMemcpyAsync(r.host_state, r.d_state, sizeof(SampleState) * ns, hipMemcpyDeviceToHost, stream);
         if (ce == hipSuccess) ce = hipStreamSynchronize(stream);
         if (ce != hipSuccess) { result = fail(ctx, OFM_EHIP, "state read-back failed: %s", hipGetErrorString(ce)); break; }
         bool all = true;
-        live_cells[0] = 0.0;
+        r.live_cells = 0.0;
         for (int i = 0; i < ns; ++i) {
-            all = all && ctx->host_state[i].done;
-            if (!ctx->host_state[i].done) live_cells[0] += (double)cells_of(mem[i].spec);
+            all = all && r.host_state[i].done;
+            if (!r.host_state[i].done) r.live_cells += (double)cells_of(r.mem[i].spec);
         }
-        if (all) break;
-        if (taken > cap + 2 * K) { result = fail(ctx, OFM_EHIP, "samples did not finish within the step cap"); break; }
+        r.state.assign(r.host_state, r.host_state + ns);
+        if (all) { r.finished = true; break; }
+        if (r.taken > r.cap + 2 * r.K) { result = fail(ctx, OFM_EHIP, "samples did not finish within the step cap"); break; }
+        if (r.taken - start >= max_steps) break;
     }
-    if (kev[0]) (void)hipEventDestroy(kev[0]);
-    if (kev[1]) (void)hipEventDestroy(kev[1]);
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
-    (void)hipEventRecord(e2, stream);
-    (void)hipEventSynchronize(e2);
-    float t01 = 0, t12 = 0;
-    (void)hipEventElapsedTime(&t01, e0, e1);
-    (void)hipEventElapsedTime(&t12, e1, e2);
+    (void)hipEventRecord(e1, stream);
+    (void)hipEventSynchronize(e1);
+    r.step_s += elapsed_s(e0, e1);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    (void)hipEventDestroy(e2);
-    if (result) return result;
-    ro.state.assign(ctx->host_state, ctx->host_state + ns);
-    ctx->last_init_s = t01 * 1e-3;
-    ctx->last_step_s = t12 * 1e-3;
+    return result;
+}
+
+// Statistics of a finished run into the context; the step sizes to the host.
+static int run_stats(ofm_run& r, double* dts_host)
+{
+    ofm_ctx* ctx = r.ctx;
+    ctx->last_init_s = r.init_s;
+    ctx->last_step_s = r.step_s;
     double cs = 0;
-    for (int i = 0; i < ns; ++i) cs += (double)cells_of(mem[i].spec) * (double)ro.state[i].steps;
+    for (size_t i = 0; i < r.mem.size(); ++i) cs += (double)cells_of(r.mem[i].spec) * (double)r.state[i].steps;
     ctx->last_cell_steps = cs;
-    if (dts_host && dts_len > 0)
-        HIPCHK(ctx, hipMemcpy(dts_host, d_dt, sizeof(double) * dts_len, hipMemcpyDeviceToHost));
+    if (dts_host && r.dts_len > 0)
+        HIPCHK(ctx, hipMemcpy(dts_host, r.d_dt, sizeof(double) * r.dts_len, hipMemcpyDeviceToHost));
     return OFM_OK;
+}
+
+// Runs members to completion.  init: 1 = build Q_0 from bubbles, 0 = use buf0.
+static int run(ofm_ctx* ctx, std::vector<Member>& mem, bool init, double* dts_host, int64_t dts_len,
+               std::vector<SampleState>& out, hipStream_t user_stream)
+{
+    ofm_run r;
+    r.mem = mem;
+    int rc = run_begin(ctx, r, init, dts_host ? dts_len : 0, user_stream);
+    if (rc == OFM_OK) rc = run_advance(r, INT64_MAX);
+    if (rc == OFM_OK) rc = run_stats(r, dts_host);
+    if (rc == OFM_OK) out = r.state;
+    return rc;
 }
 
 static void to_qoi(const ofm_solve_spec& s, const SampleState& st, ofm_qoi* q)
@@ -490,11 +601,11 @@ int ofm_step(ofm_ctx* ctx, const ofm_solve_spec* spec, ofm_state_view* st, int64
     std::vector<double> dloc;
     double* dptr = dts;
     if (!dptr) { dloc.resize(n_steps); dptr = dloc.data(); }
-    RunOut ro;
-    rc = run(ctx, mem, false, dptr, n_steps, ro, (hipStream_t)stream);
+    std::vector<SampleState> out;
+    rc = run(ctx, mem, false, dptr, n_steps, out, (hipStream_t)stream);
     if (rc) return rc;
-    to_qoi(mem[0].spec, ro.state[0], qoi);
-    if (ro.state[0].steps & 1) std::swap(st->u, st->u_tmp);
+    to_qoi(mem[0].spec, out[0], qoi);
+    if (out[0].steps & 1) std::swap(st->u, st->u_tmp);
     return OFM_OK;
 }
 
@@ -524,10 +635,10 @@ static int solve_members(ofm_ctx* ctx, const ofm_batch_item* items, int32_t n, o
         mem[i].buf1 = p; p += b;
         mem[i].du = p; p += b;
     }
-    RunOut ro;
-    rc = run(ctx, mem, true, nullptr, 0, ro, (hipStream_t)stream);
+    std::vector<SampleState> out;
+    rc = run(ctx, mem, true, nullptr, 0, out, (hipStream_t)stream);
     if (rc) return rc;
-    for (int i = 0; i < n; ++i) to_qoi(mem[i].spec, ro.state[i], qoi + i);
+    for (int i = 0; i < n; ++i) to_qoi(mem[i].spec, out[i], qoi + i);
     return OFM_OK;
 }
 
@@ -545,6 +656,76 @@ int ofm_solve(ofm_ctx* ctx, const ofm_solve_spec* spec, const double* bubbles, i
 int ofm_solve_batch(ofm_ctx* ctx, const ofm_batch_item* items, int32_t n, ofm_qoi* qoi, void* stream)
 {
     return solve_members(ctx, items, n, qoi, stream);
+}
+
+int ofm_run_begin(ofm_ctx* ctx, const ofm_batch_item* items, int32_t n, ofm_run** out, void* stream)
+{
+    if (!ctx) return fail(nullptr, OFM_EINVAL, "null context");
+    if (!items || n < 1 || !out) return fail(ctx, OFM_EINVAL, "ofm_run_begin: bad arguments");
+    *out = nullptr;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    ofm_run* r = new ofm_run();
+    r->own = true;
+    r->mem.resize(n);
+    size_t need = 0;
+    for (int i = 0; i < n; ++i) {
+        int rc = validate(ctx, items[i].spec);
+        if (rc) { delete r; return rc; }
+        if (items[i].n_bubbles < 0 || (items[i].n_bubbles > 0 && !items[i].bubbles)) {
+            delete r;
+            return fail(ctx, OFM_EINVAL, "item %d: bad bubbles", i);
+        }
+        r->mem[i].spec = *items[i].spec;
+        r->mem[i].bubbles = items[i].bubbles;
+        r->mem[i].nb = items[i].n_bubbles;
+        need += 3 * align256(state_bytes(r->mem[i].spec));
+    }
+    if (hipMalloc(&r->arena, need) != hipSuccess) {
+        r->arena = nullptr;
+        (void)hipGetLastError();
+        delete r;
+        return fail(ctx, OFM_ENOMEM, "ofm_run_begin: device allocation of %zu bytes failed", need);
+    }
+    char* p = (char*)r->arena;
+    for (int i = 0; i < n; ++i) {
+        const size_t b = align256(state_bytes(r->mem[i].spec));
+        r->mem[i].buf0 = p; p += b;
+        r->mem[i].buf1 = p; p += b;
+        r->mem[i].du = p; p += b;
+    }
+    int rc = run_begin(ctx, *r, true, 0, (hipStream_t)stream);
+    if (rc) { delete r; return rc; }
+    *out = r;
+    return OFM_OK;
+}
+
+int ofm_run_advance(ofm_run* run, int64_t max_steps, int32_t* done)
+{
+    if (!run) return fail(nullptr, OFM_EINVAL, "null run");
+    if (max_steps < 1) return fail(run->ctx, OFM_EINVAL, "ofm_run_advance: max_steps must be >= 1");
+    HIPCHK(run->ctx, hipSetDevice(run->ctx->device));
+    int rc = run_advance(*run, max_steps);
+    if (done) *done = run->finished ? 1 : 0;
+    return rc;
+}
+
+int ofm_run_status(const ofm_run* run, ofm_qoi* qoi, int64_t* steps_taken, double* init_s, double* step_s)
+{
+    if (!run) return fail(nullptr, OFM_EINVAL, "null run");
+    if (qoi)
+        for (size_t i = 0; i < run->mem.size(); ++i) to_qoi(run->mem[i].spec, run->state[i], qoi + i);
+    if (steps_taken) *steps_taken = run->taken;
+    if (init_s) *init_s = run->init_s;
+    if (step_s) *step_s = run->step_s;
+    return OFM_OK;
+}
+
+void ofm_run_destroy(ofm_run* run)
+{
+    if (!run) return;
+    (void)hipSetDevice(run->ctx->device);
+    (void)hipStreamSynchronize(run->ctx->stream);
+    delete run;
 }
 
 int ofm_last_solve_stats(const ofm_ctx* ctx, double* init_s, double* step_s, double* cell_steps)

@@ -3,8 +3,8 @@
 The driver decides which samples to run next.  It does no arithmetic of the
 method itself:
   * clouds come from ofm_sample_cloud;
-  * solves from ofm_solve_batch (coupled pairs share their bubbles) and the
-    learned level from the ofm_nn_* calls;
+  * solves from ofm_run_* (batched; coupled pairs share their bubbles) and
+    the learned level from the ofm_nn_* calls (surrogate.py);
   * moments, coefficients, errors, estimate and sample allocation come from
     the ofm_mlmc_* / ofm_ofmlmc_* kernels, all FP64 on the device.
 
@@ -12,19 +12,27 @@ Terms (Sec. 2.4.1): with fidelities f_0 < f_1 < ... < f_L, term 0 holds
 single samples of f_0 and term l >= 1 holds pairs (f_l, f_{l-1}) drawn with
 the same omega.  With a learned level, f_0 is the network and the solver
 levels follow.  Every term draws its omegas from its own stream
-(seed, term, index), so terms are independent.  W_l is the measured time
-per sample of term l (a pair costs both of its solves, Sec. 2.4.1).
+(seed, term, index), so terms are independent; the network's training set
+comes from a stream no term uses.  W_l is the measured time per sample of
+term l (a pair costs both of its solves, Sec. 2.4.1): solves of several
+terms run in one batch, and each sample is charged the batch time in
+proportion to its cell-steps (grid cells times time steps).
 
 Iteration (Sec. 2.4.4): warm-up counts (eq. (warmup), at least 2 per term)
 -> solve -> moments -> coefficients (eq. (alpha-matvec)) -> errors
 (eq. (ocv-mlmc-err)) -> stop if eps <= tau -> optimal counts (eq. (M-tol),
 keeping computed samples) -> solve the additional samples -> ...
+
+Run as a program, it runs the workloads of the method end to end (see
+`python -m paper_1705_04374_amd.driver --help`).
 """
 from __future__ import annotations
 
+import argparse
 import json
 import math
 import os
+import sys
 import time
 
 import numpy as np
@@ -32,6 +40,8 @@ import numpy as np
 from . import capi
 
 SAMPLE_OK = capi.SAMPLE_OK
+# stream of the learned level's training samples (no estimator term uses it)
+TRAIN_TERM = 1 << 20
 
 
 class Fidelity:
@@ -69,107 +79,150 @@ class Ledger:
                     f.write(json.dumps(r) + "\n")
 
 
+def state_bytes(ndim: int, n: int, precision: str) -> float:
+    """Device bytes of one solve (three state arrays)."""
+    return 3.0 * (4 + ndim) * n ** ndim * (4 if precision == "f32" else 8)
+
+
+def solve_many(ctx: capi.Context, specs: list, bubbles: list, max_batch_bytes: float = 60e9, log=print,
+               progress_seconds: float = 30.0, portion_steps: int = 16) -> tuple:
+    """Solve every (spec, bubbles) pair, batched (ofm_run_*) so that a batch
+    stays within max_batch_bytes of state; largest grids first.  Returns the
+    QoIs in input order and the wall seconds charged to each solve (its batch's
+    time in proportion to its cell-steps)."""
+    out = [None] * len(specs)
+    secs = [0.0] * len(specs)
+    order = sorted(range(len(specs)), key=lambda i: -specs[i].n)
+    batch, size = [], 0.0
+
+    def flush():
+        if not batch:
+            return
+        t0 = time.perf_counter()
+        run = capi.Run(ctx, [specs[i] for i in batch], [bubbles[i] for i in batch])
+        last = time.perf_counter()
+        try:
+            while not run.advance(portion_steps):
+                if time.perf_counter() - last >= progress_seconds:
+                    st = run.status()
+                    live = [q["t"] for q in st["qoi"] if q["status"] == SAMPLE_OK]
+                    log("    batch of %d (n = %s): %d steps, slowest t = %.3e" % (
+                        len(batch), sorted({specs[i].n for i in batch}), st["steps"], min(live) if live else 0.0))
+                    last = time.perf_counter()
+            qs = run.status()["qoi"]
+        finally:
+            run.close()
+        wall = time.perf_counter() - t0
+        work = [float(specs[i].n) ** specs[i].ndim * max(q["steps"], 1) for i, q in zip(batch, qs)]
+        tot = sum(work)
+        for i, q, w in zip(batch, qs, work):
+            out[i] = q
+            secs[i] = wall * w / tot
+
+    for i in order:
+        b = state_bytes(specs[i].ndim, specs[i].n, "f64" if specs[i].precision == capi.OFM_F64 else "f32")
+        if batch and size + b > max_batch_bytes:
+            flush()
+            batch, size = [], 0.0
+        batch.append(i)
+        size += b
+    flush()
+    return out, secs
+
+
 class OFMLMC:
     def __init__(self, ctx: capi.Context, solver_cfg: dict, cloud: dict, levels: list, precision: str = "f32",
-                 t_end: float = 0.0, n_steps: int = 0, seed: int = 0, net=None, net_scale=None,
-                 ledger: str | None = None, max_batch_bytes: float = 60e9, max_steps: int = 10 ** 6):
+                 t_end: float = 0.0, n_steps: int = 0, seed: int = 0, net=None,
+                 ledger: str | None = None, max_batch_bytes: float = 60e9, max_steps: int = 10 ** 6,
+                 log=print):
         self.ctx, self.cfg, self.cloud = ctx, solver_cfg, cloud
         self.precision, self.t_end, self.n_steps, self.seed = precision, t_end, n_steps, seed
-        self.net = net
+        self.net = net          # a surrogate.Surrogate (predict) for the learned level, or None
         self.fid = ([Fidelity("nn")] if net is not None else []) + [Fidelity("solver", n) for n in levels]
         self.L = len(self.fid) - 1
         self.ledger = Ledger(ledger)
         self.max_batch_bytes = max_batch_bytes
         self.max_steps = max_steps
+        self.log = log
         self.q = [dict(f=[], c=[], ok=[]) for _ in range(self.L + 1)]
         self.time = [0.0] * (self.L + 1)
         self.count = [0] * (self.L + 1)
         self.solve_seconds = 0.0
 
     # -- sampling -----------------------------------------------------------
-    def _spec(self, n: int):
+    def spec(self, n: int, precision: str | None = None):
         cfg = dict(self.cfg)
         cfg["n"] = n
-        return capi.make_spec(cfg, self.precision, t_end=self.t_end, n_steps=self.n_steps, max_steps=self.max_steps)
-
-    def _state_bytes(self, n: int) -> float:
-        d = self.cloud["ndim"]
-        return 3.0 * (4 + d) * n ** d * (4 if self.precision == "f32" else 8)
-
-    def _solve(self, ns: list, bubbles: list) -> list:
-        """Batched solves, split so that one batch stays within max_batch_bytes."""
-        out = [None] * len(ns)
-        order = list(range(len(ns)))
-        batch, size = [], 0.0
-        t0 = time.perf_counter()
-
-        def flush():
-            if not batch:
-                return
-            qs = capi.ofm_solve_batch(self.ctx, [self._spec(ns[i]) for i in batch], [bubbles[i] for i in batch])
-            for i, q in zip(batch, qs):
-                out[i] = q
-        for i in order:
-            b = self._state_bytes(ns[i])
-            if batch and size + b > self.max_batch_bytes:
-                flush()
-                batch, size = [], 0.0
-            batch.append(i)
-            size += b
-        flush()
-        self.solve_seconds += time.perf_counter() - t0
-        return out
+        return capi.make_spec(cfg, precision or self.precision, t_end=self.t_end, n_steps=self.n_steps,
+                              max_steps=self.max_steps)
 
     def _net_qoi(self, bubbles: list) -> np.ndarray:
-        import torch
-        sets = len(bubbles)
-        b = torch.tensor(np.concatenate(bubbles), dtype=torch.float64, device="cuda")
-        x = torch.empty((b.shape[0], 4), dtype=torch.float32, device="cuda")
-        capi.ofm_nn_features(self.cloud, b, x)
-        sizes = [len(bb) for bb in bubbles]
-        off = torch.tensor(np.concatenate([[0], np.cumsum(sizes)]), dtype=torch.int32, device="cuda")
-        y = torch.empty((sets, 5), dtype=torch.float32, device="cuda")
-        self.net.forward(x, off, y)
-        torch.cuda.synchronize()
-        return y[:, 0].double().cpu().numpy()
+        return self.net.predict(bubbles)[:, 0]
 
-    def sample(self, k: int, m_new: int):
-        """Run m_new fresh samples of term k."""
-        if m_new <= 0:
-            return
-        start = self.count[k]
-        idx = list(range(start, start + m_new))
-        todo = [i for i in idx if self.ledger.have(k, i) is None]
-        t0 = time.perf_counter()
-        if todo:
-            bubs = [capi.ofm_sample_cloud(self.cloud, self.seed, k, i) for i in todo]
+    def sample_terms(self, m_new: list):
+        """Run m_new[k] fresh samples of every term k, all solves of all terms
+        in one batched run (the learned level separately, on its kernels)."""
+        todo = {}
+        for k, m in enumerate(m_new):
+            if m > 0:
+                idx = range(self.count[k], self.count[k] + m)
+                todo[k] = [i for i in idx if self.ledger.have(k, i) is None]
+        specs, bubs, where = [], [], []
+        net_sets, net_where = [], []
+        for k, idx in todo.items():
             fine, coarse = self.fid[k], (self.fid[k - 1] if k >= 1 else None)
-            res = {}
-            for which, f in (("f", fine), ("c", coarse)):
-                if f is None:
-                    continue
-                if f.kind == "nn":
-                    vals = self._net_qoi(bubs)
-                    res[which] = [dict(p_max=float(v), status=SAMPLE_OK, steps=0) for v in vals]
-                else:
-                    res[which] = self._solve([f.n] * len(todo), bubs)
-            dt = (time.perf_counter() - t0) / len(todo)
-            rows = []
-            for j, i in enumerate(todo):
-                qf = res["f"][j]
-                qc = res["c"][j] if "c" in res else None
+            for i in idx:
+                b = capi.ofm_sample_cloud(self.cloud, self.seed, k, i)
+                for which, f in (("f", fine), ("c", coarse)):
+                    if f is None:
+                        continue
+                    if f.kind == "nn":
+                        net_sets.append(b)
+                        net_where.append((k, i, which))
+                    else:
+                        specs.append(self.spec(f.n))
+                        bubs.append(b)
+                        where.append((k, i, which))
+        res = {}
+        if specs:
+            t0 = time.perf_counter()
+            qs, secs = solve_many(self.ctx, specs, bubs, self.max_batch_bytes, self.log)
+            self.solve_seconds += time.perf_counter() - t0
+            for w, q, s in zip(where, qs, secs):
+                res[w] = (q, s)
+        if net_sets:
+            t0 = time.perf_counter()
+            vals = self._net_qoi(net_sets)
+            per = (time.perf_counter() - t0) / len(net_sets)
+            for w, v in zip(net_where, vals):
+                res[w] = (dict(p_max=float(v), status=SAMPLE_OK, steps=0, x=(0.0, 0.0, 0.0), t_at_max=0.0), per)
+        rows = []
+        for k, idx in todo.items():
+            for i in idx:
+                qf, sf = res[(k, i, "f")]
+                qc, sc = res.get((k, i, "c"), (None, 0.0))
                 ok = qf["status"] == SAMPLE_OK and (qc is None or qc["status"] == SAMPLE_OK)
                 rows.append(dict(term=k, index=i, qf=qf["p_max"], qc=qc["p_max"] if qc else None, ok=bool(ok),
                                  status_f=qf["status"], status_c=qc["status"] if qc else None,
-                                 xf=list(qf.get("x", ())), tf=qf.get("t_at_max"), seconds=dt))
-            self.ledger.add(rows)
-        for i in idx:
-            r = self.ledger.have(k, i)
-            self.q[k]["f"].append(r["qf"])
-            self.q[k]["c"].append(r["qc"] if r["qc"] is not None else 0.0)
-            self.q[k]["ok"].append(1 if r["ok"] else 0)
-            self.time[k] += r["seconds"]
-        self.count[k] += m_new
+                                 xf=list(qf.get("x", ())), tf=qf.get("t_at_max"), steps_f=qf.get("steps", 0),
+                                 steps_c=qc.get("steps", 0) if qc else 0, seconds=sf + sc))
+        self.ledger.add(rows)
+        for k, m in enumerate(m_new):
+            if m <= 0:
+                continue
+            for i in range(self.count[k], self.count[k] + m):
+                r = self.ledger.have(k, i)
+                self.q[k]["f"].append(r["qf"])
+                self.q[k]["c"].append(r["qc"] if r["qc"] is not None else 0.0)
+                self.q[k]["ok"].append(1 if r["ok"] else 0)
+                self.time[k] += r["seconds"]
+            self.count[k] += m
+
+    def sample(self, k: int, m_new: int):
+        """Run m_new fresh samples of term k."""
+        m = [0] * (self.L + 1)
+        m[k] = m_new
+        self.sample_terms(m)
 
     # -- estimator (device kernels) -------------------------------------------
     def moments(self):
@@ -220,31 +273,35 @@ class OFMLMC:
         return out.cpu().tolist(), int(flag.item())
 
     def run(self, rel_tol: float = 0.01, warmup=None, W_model=None, max_iter: int = 10, min_samples: int = 2,
-            max_new_finest: int | None = None, log=print) -> dict:
+            max_samples=None, log=None) -> dict:
         """Adaptive loop to eps <= rel_tol |E|.  warmup: explicit counts, or
-        eq. (warmup) from W_model (relative cost per term)."""
+        eq. (warmup) from W_model (relative cost per term).  max_samples:
+        optional cap per term (None entries = no cap)."""
+        log = log or self.log
         L = self.L
+        cap = max_samples or [None] * (L + 1)
         if warmup is None:
             W0 = W_model
             warmup = [max(min_samples, int(math.ceil(W0[L] / W0[k] / 2.0 ** (L - k)))) for k in range(L + 1)]
+        warmup = [min(w, c) if c else w for w, c in zip(warmup, cap)]
         history = []
         t_start = time.perf_counter()
         target = list(warmup)
         for it in range(max_iter):
-            for k in range(L + 1):
-                self.sample(k, max(0, target[k] - self.count[k]))
+            self.sample_terms([max(0, target[k] - self.count[k]) for k in range(L + 1)])
             W = self.work()
             res = self.evaluate(W)
             tau = rel_tol * abs(res["E"])
-            res.update(iteration=it, tau=tau, counts=list(self.count), seconds=time.perf_counter() - t_start)
+            res.update(iteration=it, tau=tau, counts=list(self.count), seconds=time.perf_counter() - t_start,
+                       sample_seconds=list(self.time))
             history.append(res)
-            log("iter %d: E=%.6e eps=%.3e tau=%.3e M=%s alpha=%s" % (it, res["E"], res["eps"], tau, self.count,
-                                                                     [round(a, 4) for a in res["alpha"]]))
+            log("iter %d: E=%.6e eps=%.3e tau=%.3e M=%s alpha=%s W=%s" % (
+                it, res["E"], res["eps"], tau, self.count, [round(a, 4) for a in res["alpha"]],
+                ["%.3g" % w for w in W]))
             if res["eps"] <= tau:
                 break
             M, flag = self.allocate(res["sigma_t2"], W, tau)
-            if max_new_finest is not None:
-                M[L] = min(M[L], self.count[L] + max_new_finest)
+            M = [min(m, c) if c else m for m, c in zip(M, cap)]
             target = [max(m, c) for m, c in zip(M, self.count)]
             if target == self.count:
                 break
@@ -252,4 +309,162 @@ class OFMLMC:
         out["history"] = history
         out["wall_seconds"] = time.perf_counter() - t_start
         out["fidelities"] = [repr(f) for f in self.fid]
+        out["cost_seconds"] = sum(self.time)
         return out
+
+
+# ---------------------------------------------------------------------------
+# The learned level: training set, fit, persistence
+# ---------------------------------------------------------------------------
+def save_surrogate(sur, path: str):
+    import torch
+    p = torch.empty(capi.SetNet.param_count(), dtype=torch.float32, device="cuda")
+    sur.net.get_params(p)
+    np.savez(path, params=p.cpu().numpy(), out_mean=np.array(sur.info["out_mean"]),
+             out_std=np.array(sur.info["out_std"]), info=json.dumps(sur.info))
+
+
+def load_surrogate(ctx, cloud, path: str, seed: int = 0):
+    import torch
+    from .surrogate import Surrogate
+    z = np.load(path)
+    sur = Surrogate(ctx, cloud, seed=seed)
+    sur.net = capi.SetNet(ctx, 1.0 / float(cloud["n_bubbles"]), seed=seed,
+                          out_mean=tuple(float(v) for v in z["out_mean"]),
+                          out_std=tuple(float(v) for v in z["out_std"]))
+    sur.net.set_params(torch.tensor(z["params"], device="cuda"))
+    sur.info = json.loads(str(z["info"]))
+    return sur
+
+
+def train_level(ctx, cloud, cfg, n: int, count: int, t_end: float, seed: int, precision: str = "f32",
+                log=print, epochs: int = 300, ledger: str | None = None) -> tuple:
+    """Solve `count` training clouds (stream TRAIN_TERM) at grid n and fit the
+    set network on their QoIs.  Returns (surrogate, info)."""
+    from .surrogate import Surrogate
+    bubs = [capi.ofm_sample_cloud(cloud, seed, TRAIN_TERM, i) for i in range(count)]
+    led = Ledger(ledger)
+    todo = [i for i in range(count) if led.have(TRAIN_TERM, i) is None]
+    c = dict(cfg)
+    c["n"] = n
+    spec = capi.make_spec(c, precision, t_end=t_end)
+    t0 = time.perf_counter()
+    if todo:
+        log("  training solves: %d at %d^%d" % (len(todo), n, cfg["ndim"]))
+        qs, secs = solve_many(ctx, [spec] * len(todo), [bubs[i] for i in todo], log=log)
+        led.add([dict(term=TRAIN_TERM, index=i, q=q, seconds=s) for i, q, s in zip(todo, qs, secs)])
+    solve_s = time.perf_counter() - t0
+    qois = [led.have(TRAIN_TERM, i)["q"] for i in range(count)]
+    sur = Surrogate(ctx, cloud, seed=seed)
+    t1 = time.perf_counter()
+    info = sur.fit(bubs, qois, epochs=epochs, log=log)
+    info.update(solve_seconds=solve_s, fit_seconds=time.perf_counter() - t1,
+                solve_seconds_charged=sum(led.have(TRAIN_TERM, i)["seconds"] for i in range(count)))
+    return sur, info
+
+
+def variance_reduction(res: dict, term: int = 1) -> dict:
+    """What the learned level gains on a pair term (solver level, network):
+    the variance of the solver level alone against the pair term's variance
+    with the estimator's coefficient."""
+    vf, vc, cv = res["var_f"][term], res["var_c"][term], res["cov"][term]
+    st2 = res["sigma_t2"][term]
+    return dict(var_solver=vf, var_pair_term=st2, factor=vf / st2 if st2 > 0 else None,
+                alpha_nn=res["alpha"][term - 1],
+                correlation=cv / math.sqrt(vf * vc) if vf > 0 and vc > 0 else None)
+
+
+# ---------------------------------------------------------------------------
+# Workloads of the method, end to end
+# ---------------------------------------------------------------------------
+WORKLOADS = {
+    # 2-D FP64 plain method: 2 levels, fixed counts
+    "mlmc2d": dict(cloud="cloud2d", levels=[32, 64], counts=[16, 4], precision="f64"),
+    # batched 3-level, FP32 stencil / FP64 statistics, fixed counts
+    "batched3": dict(cloud="cloud500", levels=[64, 128, 256], counts=[256, 48, 8], precision="f32"),
+    # learned level trained on 4096 solves at 64^3, then 65536 network
+    # evaluations and 512 (64^3, network) pairs
+    "surrogate": dict(cloud="cloud500", n_train=64, count_train=4096, M_nn=65536, M_pairs=512, precision="f32"),
+    # full OF-MLMC, learned level + 4 solver levels, to 1 % relative RMSE
+    "ofmlmc": dict(cloud="cloud500", levels=[64, 128, 256, 512], n_train=64, count_train=4096, M_nn=65536,
+                   precision="f32"),
+}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(prog="python -m paper_1705_04374_amd.driver",
+                                 description="Run a workload of the OF-MLMC method end to end.")
+    ap.add_argument("workload", choices=sorted(WORKLOADS))
+    ap.add_argument("--dir", default="ofmlmc_run", help="folder for the ledgers, the network and the result")
+    ap.add_argument("--rel-tol", type=float, default=0.01)
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--max-iter", type=int, default=10)
+    a = ap.parse_args(argv)
+    from workloads.configs import MASTER_SEED, cloud_spec, solver_config, t_end
+    os.makedirs(a.dir, exist_ok=True)
+    w = WORKLOADS[a.workload]
+    cloud = cloud_spec(w["cloud"])
+    T = t_end(w["cloud"])
+    seed = MASTER_SEED
+
+    def log(*x):
+        print(*x, flush=True)
+
+    ctx = capi.Context(0)
+    out = dict(workload=a.workload, t_end=T, spec=w)
+    ledger = os.path.join(a.dir, "ledger_%s.jsonl" % a.workload)
+    net_path = os.path.join(a.dir, "surrogate.npz")
+    train_ledger = os.path.join(a.dir, "ledger_train.jsonl")
+    if a.workload in ("mlmc2d", "batched3"):
+        cfg = solver_config(w["cloud"], w["levels"][0])
+        mc = OFMLMC(ctx, cfg, cloud, w["levels"], w["precision"], t_end=T, seed=seed, ledger=ledger, log=log)
+        t0 = time.perf_counter()
+        mc.sample_terms(w["counts"])
+        out["wall_seconds"] = time.perf_counter() - t0
+        W = mc.work()
+        out["ofmlmc"] = mc.evaluate(W)
+        out["mlmc"] = mc.evaluate(W, classical=True)
+        out["cost_seconds"] = sum(mc.time)
+    elif a.workload == "surrogate":
+        cfg = solver_config(w["cloud"], w["n_train"])
+        sur, info = train_level(ctx, cloud, cfg, w["n_train"], w["count_train"], T, seed, w["precision"],
+                                log=log, epochs=a.epochs, ledger=train_ledger)
+        save_surrogate(sur, net_path)
+        out["training"] = info
+        mc = OFMLMC(ctx, cfg, cloud, [w["n_train"]], w["precision"], t_end=T, seed=seed, net=sur, ledger=ledger,
+                    log=log)
+        mc.sample_terms([w["M_nn"], w["M_pairs"]])
+        r = mc.evaluate(mc.work())
+        out["ofmlmc"] = r
+        out["variance_reduction"] = variance_reduction(r, 1)
+    else:
+        cfg = solver_config(w["cloud"], w["levels"][0])
+        if os.path.exists(net_path):
+            sur = load_surrogate(ctx, cloud, net_path, seed=seed)
+        else:
+            sur, _ = train_level(ctx, cloud, cfg, w["n_train"], w["count_train"], T, seed, w["precision"],
+                                 log=log, epochs=a.epochs, ledger=train_ledger)
+            save_surrogate(sur, net_path)
+        out["training"] = sur.info
+        mc = OFMLMC(ctx, cfg, cloud, w["levels"], w["precision"], t_end=T, seed=seed, net=sur, ledger=ledger,
+                    log=log)
+        # model costs for the warm-up (eq. (warmup)): a solve at n costs
+        # n^(d+1) (cells x steps), a pair both of its solves, the network ~0
+        d = cfg["ndim"]
+        single = [1e-6] + [float(n) ** (d + 1) for n in w["levels"]]
+        W_model = [single[0], single[1]] + [single[k] + single[k - 1] for k in range(2, len(single))]
+        res = mc.run(rel_tol=a.rel_tol, W_model=W_model, max_iter=a.max_iter,
+                     max_samples=[w["M_nn"]] + [None] * len(w["levels"]))
+        out["ofmlmc"] = res
+        out["variance_reduction"] = variance_reduction(res, 1)
+    path = os.path.join(a.dir, "result_%s.json" % a.workload)
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1, default=float)
+    log("wrote", path)
+    ctx.close()
+    return out
+
+
+if __name__ == "__main__":
+    main()
+    sys.exit(0)

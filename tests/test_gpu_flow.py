@@ -243,6 +243,40 @@ def test_batch_equals_single_solves(ctx):
     assert math.isclose(qb[3]["p_max"], ref["p_max"], rel_tol=1e-9) and qb[3]["steps"] == ref["steps"]
 
 
+def test_run_in_portions_equals_batch(ctx):
+    """A run handle advanced a few steps at a time gives the batch solve's
+    QoIs bit for bit, reports progress in between, and a second handle on the
+    same context can run at the same time."""
+    from paper_1705_04374_amd import capi
+    say("run handle")
+    T = 6.0e-4
+    specs, bubs = [], []
+    for i, n in enumerate([32, 16, 24]):
+        specs.append(capi.make_spec(solver_config("cloud2d", n), "f64", t_end=T))
+        bubs.append(sample_cloud(cloud_spec("cloud2d"), MASTER_SEED, 3, i))
+    ref = capi.ofm_solve_batch(ctx, specs, bubs)
+    run = capi.Run(ctx, specs, bubs)
+    other = capi.Run(ctx, specs[1:2], bubs[1:2])
+    portions, last_t = 0, 0.0
+    while not run.advance(3):
+        portions += 1
+        st = run.status()
+        assert all(q["status"] == capi.SAMPLE_OK for q in st["qoi"])
+        t_min = min(q["t"] for q in st["qoi"])
+        assert 0.0 < t_min < T and st["steps"] >= 3 * portions
+        assert max(q["t"] for q in st["qoi"]) >= last_t
+        last_t = max(q["t"] for q in st["qoi"])
+    assert portions >= 2
+    got = run.status()["qoi"]
+    assert got == ref
+    assert not other.advance(2)              # interleaved with the first run
+    while not other.advance(50):
+        pass
+    assert other.status()["qoi"][0] == ref[1]
+    run.close()
+    other.close()
+
+
 def test_failure_status_and_step_cap(ctx):
     import torch
     from paper_1705_04374_amd import capi
