@@ -116,15 +116,24 @@ static double mix_pi(const orc_spec* s, double a2)
 }
 
 /* K of eq. (var_K), with rho_k c_k^2 = gamma_k (p + pc_k) for a stiffened
- * gas, evaluated at a cell centre with a2 clamped to [0, 1]. */
+ * gas, evaluated at a cell centre with a2 clamped to [0, 1].
+ * Reading where the paper is silent: a phase whose pressure is below its own
+ * range (p + pc_k < 0, e.g. a trace of gas in water under tension) has no
+ * stiffness, rho_k c_k^2 = 0.  Then a2 + K = a2 r1 / (a1 r2 + a2 r1) stays in
+ * [0, 1] (= 1 when only the gas is out of range: it takes all of the volume
+ * change), where the unfloored formula has a vanishing denominator.  K = 0
+ * when both phases are out of range. */
 double orc_k_coefficient(const orc_spec* s, double a2, double p)
 {
     double a = a2 < 0.0 ? 0.0 : (a2 > 1.0 ? 1.0 : a2);
     double b = 1.0 - a;
     double rc1 = s->gamma1 * (p + s->pc1);
     double rc2 = s->gamma2 * (p + s->pc2);
-    if (a == 0.0 || a == 1.0) return 0.0;
-    return b * a * (rc1 - rc2) / (b * rc2 + a * rc1);
+    if (rc1 < 0.0) rc1 = 0.0;
+    if (rc2 < 0.0) rc2 = 0.0;
+    double den = b * rc2 + a * rc1;
+    if (a == 0.0 || a == 1.0 || !(den > 0.0)) return 0.0;
+    return b * a * (rc1 - rc2) / den;
 }
 
 /* Number of stored variables: a1r1, a2r2, ndim momenta, E, a2. */

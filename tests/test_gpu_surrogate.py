@@ -28,8 +28,8 @@ def test_learned_level_reduces_the_pair_variance(tmp_path):
     cfg = solver_config("cloud2d", 32)
     say("training set and fit")
     sur, info = train_level(ctx, cloud, cfg, 32, 1024, T, MASTER_SEED, "f32", log=say, epochs=150)
-    say("  ", {k: info[k] for k in ("n_train", "epochs", "best_epoch", "val_loss", "train_loss")})
-    assert info["val_loss"] < 0.8            # standardised MSE over the 5 outputs: it learnt something
+    say("  ", {k: info[k] for k in ("n_train", "epochs", "best_epoch", "val_corr_pmax", "val_loss", "train_loss")})
+    assert info["val_corr_pmax"] > 0.5        # validation correlation of the p_max prediction
     # persistence round trip gives the same predictions
     path = str(tmp_path / "net.npz")
     save_surrogate(sur, path)
