@@ -117,23 +117,25 @@ static double mix_pi(const orc_spec* s, double a2)
 
 /* K of eq. (var_K), with rho_k c_k^2 = gamma_k (p + pc_k) for a stiffened
  * gas, evaluated at a cell centre with a2 clamped to [0, 1].
- * Reading where the paper is silent: a phase whose pressure is below its own
- * range (p + pc_k < 0, e.g. a trace of gas in water under tension) has no
- * stiffness, rho_k c_k^2 = 0.  Then a2 + K = a2 r1 / (a1 r2 + a2 r1) stays in
- * [0, 1] (= 1 when only the gas is out of range: it takes all of the volume
- * change), where the unfloored formula has a vanishing denominator.  K = 0
- * when both phases are out of range. */
+ * Reading where the paper is silent: a2 + K, the share of the mixture's
+ * volume change taken by the gas (= a2 r1 / (a1 r2 + a2 r1)), is kept in
+ * [0, 1].  The formula leaves that range only when a phase is below its
+ * stiffened-gas range (p + pc_k < 0, e.g. a trace of gas in water under
+ * tension), where its denominator a1 r2 + a2 r1 can vanish and K diverge;
+ * there K is clamped so that a2 + K is 0 or 1.  K = 0 in pure phases and
+ * where the denominator is exactly zero. */
 double orc_k_coefficient(const orc_spec* s, double a2, double p)
 {
     double a = a2 < 0.0 ? 0.0 : (a2 > 1.0 ? 1.0 : a2);
     double b = 1.0 - a;
     double rc1 = s->gamma1 * (p + s->pc1);
     double rc2 = s->gamma2 * (p + s->pc2);
-    if (rc1 < 0.0) rc1 = 0.0;
-    if (rc2 < 0.0) rc2 = 0.0;
     double den = b * rc2 + a * rc1;
-    if (a == 0.0 || a == 1.0 || !(den > 0.0)) return 0.0;
-    return b * a * (rc1 - rc2) / den;
+    if (a == 0.0 || a == 1.0 || den == 0.0) return 0.0;
+    double k = b * a * (rc1 - rc2) / den;
+    if (a + k < 0.0) k = -a;
+    else if (a + k > 1.0) k = 1.0 - a;
+    return k;
 }
 
 /* Number of stored variables: a1r1, a2r2, ndim momenta, E, a2. */

@@ -270,20 +270,21 @@ __device__ __forceinline__ void hllc(const Phys<T>& ph, const T (&wl)[4 + ND], c
     f[NV] = uf;
 }
 
-// K of eq. (var_K) at a cell centre, a2 clamped to [0, 1].  A phase whose
-// pressure is below its range (p + pc_k < 0) has no stiffness (rho_k c_k^2
-// taken as 0), which keeps a2 + K = a2 r1 / (a1 r2 + a2 r1) in [0, 1]; K = 0
-// when both phases are below their range.
+// K of eq. (var_K) at a cell centre, a2 clamped to [0, 1], with a2 + K (the
+// gas's share of the mixture's volume change) kept in [0, 1]: the formula
+// leaves that range only when a phase is below its stiffened-gas range
+// (p + pc_k < 0), where its denominator can vanish.
 template <typename T>
 __device__ __forceinline__ T k_coef(const Phys<T>& ph, T a2, T p)
 {
     T a = fmin(fmax(a2, T(0)), T(1));
     T b = T(1) - a;
-    T rc1 = fmax(ph.gam1 * (p + ph.pc1), T(0));
-    T rc2 = fmax(ph.gam2 * (p + ph.pc2), T(0));
+    T rc1 = ph.gam1 * (p + ph.pc1);
+    T rc2 = ph.gam2 * (p + ph.pc2);
     T den = b * rc2 + a * rc1;
     T k = a * b * (rc1 - rc2) * Num<T>::rcp(den);
-    return (a == T(0) || a == T(1) || !(den > T(0))) ? T(0) : k;
+    k = a + k < T(0) ? -a : (a + k > T(1) ? T(1) - a : k);
+    return (a == T(0) || a == T(1) || den == T(0)) ? T(0) : k;
 }
 
 // Running reduction of one thread (CFL speed, QoI, failure counters).
