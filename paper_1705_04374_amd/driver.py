@@ -79,25 +79,49 @@ class Ledger:
                     f.write(json.dumps(r) + "\n")
 
 
+class Deadline(Exception):
+    """Raised before a batch that would not finish by the driver's deadline
+    (the ledger keeps every finished sample; a later run resumes)."""
+
+
+# cell-steps per second assumed when predicting a batch's duration against a
+# deadline (conservative for the FP32 kernels; double for FP64)
+PREDICT_RATE = {"f32": 2.0e9, "f64": 0.8e9}
+
+
 def state_bytes(ndim: int, n: int, precision: str) -> float:
     """Device bytes of one solve (three state arrays)."""
     return 3.0 * (4 + ndim) * n ** ndim * (4 if precision == "f32" else 8)
 
 
 def solve_many(ctx: capi.Context, specs: list, bubbles: list, max_batch_bytes: float = 60e9, log=print,
-               progress_seconds: float = 30.0, portion_steps: int = 16) -> tuple:
+               progress_seconds: float = 30.0, portion_steps: int = 16, deadline: float | None = None,
+               done=None) -> tuple:
     """Solve every (spec, bubbles) pair, batched (ofm_run_*) so that a batch
     stays within max_batch_bytes of state; largest grids first.  Returns the
     QoIs in input order and the wall seconds charged to each solve (its batch's
-    time in proportion to its cell-steps)."""
+    time in proportion to its cell-steps).  deadline: a time.time() value;
+    a batch predicted to end after it is not started (Deadline is raised).
+    done(indices, qois, seconds): called after every batch."""
     out = [None] * len(specs)
     secs = [0.0] * len(specs)
     order = sorted(range(len(specs)), key=lambda i: -specs[i].n)
     batch, size = [], 0.0
 
+    def predict(idx):
+        cs = 0.0
+        for i in idx:
+            s = specs[i]
+            steps = s.n_steps if s.n_steps > 0 else 6.0 * s.n     # CFL steps to the end time, about
+            cs += float(s.n) ** s.ndim * steps
+        return cs / PREDICT_RATE["f64" if specs[idx[0]].precision == capi.OFM_F64 else "f32"]
+
     def flush():
         if not batch:
             return
+        if deadline is not None and time.time() + predict(batch) + 10.0 > deadline:
+            raise Deadline("batch of %d solves (about %.0f s) would end after the deadline" % (
+                len(batch), predict(batch)))
         t0 = time.perf_counter()
         run = capi.Run(ctx, [specs[i] for i in batch], [bubbles[i] for i in batch])
         last = time.perf_counter()
@@ -118,6 +142,8 @@ def solve_many(ctx: capi.Context, specs: list, bubbles: list, max_batch_bytes: f
         for i, q, w in zip(batch, qs, work):
             out[i] = q
             secs[i] = wall * w / tot
+        if done is not None:
+            done(list(batch), [out[i] for i in batch], [secs[i] for i in batch])
 
     for i in order:
         b = state_bytes(specs[i].ndim, specs[i].n, "f64" if specs[i].precision == capi.OFM_F64 else "f32")
@@ -134,7 +160,7 @@ class OFMLMC:
     def __init__(self, ctx: capi.Context, solver_cfg: dict, cloud: dict, levels: list, precision: str = "f32",
                  t_end: float = 0.0, n_steps: int = 0, seed: int = 0, net=None,
                  ledger: str | None = None, max_batch_bytes: float = 60e9, max_steps: int = 10 ** 6,
-                 log=print):
+                 log=print, deadline: float | None = None):
         self.ctx, self.cfg, self.cloud = ctx, solver_cfg, cloud
         self.precision, self.t_end, self.n_steps, self.seed = precision, t_end, n_steps, seed
         self.net = net          # a surrogate.Surrogate (predict) for the learned level, or None
@@ -144,6 +170,7 @@ class OFMLMC:
         self.max_batch_bytes = max_batch_bytes
         self.max_steps = max_steps
         self.log = log
+        self.deadline = deadline
         self.q = [dict(f=[], c=[], ok=[]) for _ in range(self.L + 1)]
         self.time = [0.0] * (self.L + 1)
         self.count = [0] * (self.L + 1)
@@ -161,7 +188,9 @@ class OFMLMC:
 
     def sample_terms(self, m_new: list):
         """Run m_new[k] fresh samples of every term k, all solves of all terms
-        in one batched run (the learned level separately, on its kernels)."""
+        in batched runs (the learned level separately, on its kernels).  Each
+        sample enters the ledger as soon as its solves are done, so that a run
+        stopped at its deadline resumes without repeating them."""
         todo = {}
         for k, m in enumerate(m_new):
             if m > 0:
@@ -169,10 +198,12 @@ class OFMLMC:
                 todo[k] = [i for i in idx if self.ledger.have(k, i) is None]
         specs, bubs, where = [], [], []
         net_sets, net_where = [], []
+        need = {}
         for k, idx in todo.items():
             fine, coarse = self.fid[k], (self.fid[k - 1] if k >= 1 else None)
             for i in idx:
                 b = capi.ofm_sample_cloud(self.cloud, self.seed, k, i)
+                need[(k, i)] = 2 if coarse is not None else 1
                 for which, f in (("f", fine), ("c", coarse)):
                     if f is None:
                         continue
@@ -184,21 +215,12 @@ class OFMLMC:
                         bubs.append(b)
                         where.append((k, i, which))
         res = {}
-        if specs:
-            t0 = time.perf_counter()
-            qs, secs = solve_many(self.ctx, specs, bubs, self.max_batch_bytes, self.log)
-            self.solve_seconds += time.perf_counter() - t0
-            for w, q, s in zip(where, qs, secs):
-                res[w] = (q, s)
-        if net_sets:
-            t0 = time.perf_counter()
-            vals = self._net_qoi(net_sets)
-            per = (time.perf_counter() - t0) / len(net_sets)
-            for w, v in zip(net_where, vals):
-                res[w] = (dict(p_max=float(v), status=SAMPLE_OK, steps=0, x=(0.0, 0.0, 0.0), t_at_max=0.0), per)
-        rows = []
-        for k, idx in todo.items():
-            for i in idx:
+
+        def settle(keys):
+            rows = []
+            for (k, i) in keys:
+                if need[(k, i)] != 0 or self.ledger.have(k, i) is not None:
+                    continue
                 qf, sf = res[(k, i, "f")]
                 qc, sc = res.get((k, i, "c"), (None, 0.0))
                 ok = qf["status"] == SAMPLE_OK and (qc is None or qc["status"] == SAMPLE_OK)
@@ -206,7 +228,30 @@ class OFMLMC:
                                  status_f=qf["status"], status_c=qc["status"] if qc else None,
                                  xf=list(qf.get("x", ())), tf=qf.get("t_at_max"), steps_f=qf.get("steps", 0),
                                  steps_c=qc.get("steps", 0) if qc else 0, seconds=sf + sc))
-        self.ledger.add(rows)
+            self.ledger.add(rows)
+
+        def got(w, q, s):
+            res[w] = (q, s)
+            need[(w[0], w[1])] -= 1
+
+        if net_sets:
+            t0 = time.perf_counter()
+            vals = self._net_qoi(net_sets)
+            per = (time.perf_counter() - t0) / len(net_sets)
+            for w, v in zip(net_where, vals):
+                got(w, dict(p_max=float(v), status=SAMPLE_OK, steps=0, x=(0.0, 0.0, 0.0), t_at_max=0.0), per)
+            settle({(w[0], w[1]) for w in net_where})
+        if specs:
+            def done(idx, qs, secs):
+                for j, q, s in zip(idx, qs, secs):
+                    got(where[j], q, s)
+                settle({(where[j][0], where[j][1]) for j in idx})
+            t0 = time.perf_counter()
+            try:
+                solve_many(self.ctx, specs, bubs, self.max_batch_bytes, self.log, deadline=self.deadline,
+                           done=done)
+            finally:
+                self.solve_seconds += time.perf_counter() - t0
         for k, m in enumerate(m_new):
             if m <= 0:
                 continue
@@ -338,7 +383,7 @@ def load_surrogate(ctx, cloud, path: str, seed: int = 0):
 
 
 def train_level(ctx, cloud, cfg, n: int, count: int, t_end: float, seed: int, precision: str = "f32",
-                log=print, epochs: int = 300, ledger: str | None = None) -> tuple:
+                log=print, epochs: int = 300, ledger: str | None = None, deadline: float | None = None) -> tuple:
     """Solve `count` training clouds (stream TRAIN_TERM) at grid n and fit the
     set network on their QoIs.  Returns (surrogate, info)."""
     from .surrogate import Surrogate
@@ -351,8 +396,10 @@ def train_level(ctx, cloud, cfg, n: int, count: int, t_end: float, seed: int, pr
     t0 = time.perf_counter()
     if todo:
         log("  training solves: %d at %d^%d" % (len(todo), n, cfg["ndim"]))
-        qs, secs = solve_many(ctx, [spec] * len(todo), [bubs[i] for i in todo], log=log)
-        led.add([dict(term=TRAIN_TERM, index=i, q=q, seconds=s) for i, q, s in zip(todo, qs, secs)])
+        def done(idx, qs, secs):
+            led.add([dict(term=TRAIN_TERM, index=todo[j], q=q, seconds=s) for j, q, s in zip(idx, qs, secs)])
+        solve_many(ctx, [spec] * len(todo), [bubs[i] for i in todo], log=log, deadline=deadline, done=done,
+                   max_batch_bytes=24e9)
     solve_s = time.perf_counter() - t0
     qois = [led.have(TRAIN_TERM, i)["q"] for i in range(count)]
     sur = Surrogate(ctx, cloud, seed=seed)
@@ -399,7 +446,10 @@ def main(argv=None):
     ap.add_argument("--rel-tol", type=float, default=0.01)
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--max-iter", type=int, default=10)
+    ap.add_argument("--time-limit", type=float, default=0.0,
+                    help="seconds; batches that would end later are not started (exit status 3, resume later)")
     a = ap.parse_args(argv)
+    deadline = time.time() + a.time_limit if a.time_limit > 0 else None
     from workloads.configs import MASTER_SEED, cloud_spec, solver_config, t_end
     os.makedirs(a.dir, exist_ok=True)
     w = WORKLOADS[a.workload]
@@ -411,13 +461,30 @@ def main(argv=None):
         print(*x, flush=True)
 
     ctx = capi.Context(0)
+    try:
+        out = _run_workload(a, w, ctx, cloud, T, seed, deadline, log)
+    except Deadline as e:
+        log("stopped before the deadline:", e, "- the ledgers in", a.dir, "resume the run")
+        ctx.close()
+        sys.exit(3)
+    path = os.path.join(a.dir, "result_%s.json" % a.workload)
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1, default=float)
+    log("wrote", path)
+    ctx.close()
+    return out
+
+
+def _run_workload(a, w, ctx, cloud, T, seed, deadline, log) -> dict:
+    from workloads.configs import solver_config
     out = dict(workload=a.workload, t_end=T, spec=w)
     ledger = os.path.join(a.dir, "ledger_%s.jsonl" % a.workload)
     net_path = os.path.join(a.dir, "surrogate.npz")
     train_ledger = os.path.join(a.dir, "ledger_train.jsonl")
     if a.workload in ("mlmc2d", "batched3"):
         cfg = solver_config(w["cloud"], w["levels"][0])
-        mc = OFMLMC(ctx, cfg, cloud, w["levels"], w["precision"], t_end=T, seed=seed, ledger=ledger, log=log)
+        mc = OFMLMC(ctx, cfg, cloud, w["levels"], w["precision"], t_end=T, seed=seed, ledger=ledger, log=log,
+                    deadline=deadline)
         t0 = time.perf_counter()
         mc.sample_terms(w["counts"])
         out["wall_seconds"] = time.perf_counter() - t0
@@ -428,11 +495,11 @@ def main(argv=None):
     elif a.workload == "surrogate":
         cfg = solver_config(w["cloud"], w["n_train"])
         sur, info = train_level(ctx, cloud, cfg, w["n_train"], w["count_train"], T, seed, w["precision"],
-                                log=log, epochs=a.epochs, ledger=train_ledger)
+                                log=log, epochs=a.epochs, ledger=train_ledger, deadline=deadline)
         save_surrogate(sur, net_path)
         out["training"] = info
         mc = OFMLMC(ctx, cfg, cloud, [w["n_train"]], w["precision"], t_end=T, seed=seed, net=sur, ledger=ledger,
-                    log=log)
+                    log=log, deadline=deadline)
         mc.sample_terms([w["M_nn"], w["M_pairs"]])
         r = mc.evaluate(mc.work())
         out["ofmlmc"] = r
@@ -443,11 +510,11 @@ def main(argv=None):
             sur = load_surrogate(ctx, cloud, net_path, seed=seed)
         else:
             sur, _ = train_level(ctx, cloud, cfg, w["n_train"], w["count_train"], T, seed, w["precision"],
-                                 log=log, epochs=a.epochs, ledger=train_ledger)
+                                 log=log, epochs=a.epochs, ledger=train_ledger, deadline=deadline)
             save_surrogate(sur, net_path)
         out["training"] = sur.info
         mc = OFMLMC(ctx, cfg, cloud, w["levels"], w["precision"], t_end=T, seed=seed, net=sur, ledger=ledger,
-                    log=log)
+                    log=log, deadline=deadline)
         # model costs for the warm-up (eq. (warmup)): a solve at n costs
         # n^(d+1) (cells x steps), a pair both of its solves, the network ~0
         d = cfg["ndim"]
@@ -457,11 +524,6 @@ def main(argv=None):
                      max_samples=[w["M_nn"]] + [None] * len(w["levels"]))
         out["ofmlmc"] = res
         out["variance_reduction"] = variance_reduction(res, 1)
-    path = os.path.join(a.dir, "result_%s.json" % a.workload)
-    with open(path, "w") as f:
-        json.dump(out, f, indent=1, default=float)
-    log("wrote", path)
-    ctx.close()
     return out
 
 
