@@ -152,6 +152,8 @@ struct ofm_run {
     ofm::SampleDesc* d_desc = nullptr;
     ofm::TilePartial* d_part = nullptr;
     double* d_dt = nullptr;
+    ofm::WorkItem* d_work = nullptr;
+    std::vector<int> order;                 // samples, larger grids first
     int64_t dts_len = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -185,6 +187,57 @@ static double elapsed_s(hipEvent_t a, hipEvent_t b)
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, a, b);
     return ms * 1e-3;
+}
+
+// Capture K steps of the run (its current work list) into r.gexec.
+static int run_capture(ofm_run& r)
+{
+    ofm_ctx* ctx = r.ctx;
+    hipStream_t stream = ctx->stream;
+    const ofm_solve_spec& s0 = r.mem[0].spec;
+    const int ns = (int)r.mem.size();
+    if (r.gexec) { (void)hipGraphExecDestroy(r.gexec); r.gexec = nullptr; }
+    if (r.graph) { (void)hipGraphDestroy(r.graph); r.graph = nullptr; }
+    HIPCHK(ctx, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    int rc = OFM_OK;
+    for (int g = 0; g < r.K && rc == OFM_OK; ++g)
+        for (int stg = 0; stg < 3 && rc == OFM_OK; ++stg) {
+            r.la.src = (g + stg) & 1;     // replayed at even step indices only
+            hipError_t le = launch_stage(s0.precision, s0.ndim, r.tc.tx, r.tc.ty, r.la, stg, stream);
+            if (le == hipSuccess && stg == 2)
+                le = launch_finalize(r.d_desc, r.d_state, r.d_part, ns, 0, r.d_dt, r.dts_len, stream);
+            if (le != hipSuccess) rc = fail(ctx, OFM_EHIP, "launch failed: %s", hipGetErrorString(le));
+        }
+    hipError_t ce = hipStreamEndCapture(stream, &r.graph);
+    if (rc) return rc;
+    if (ce != hipSuccess) return fail(ctx, OFM_EHIP, "graph capture failed: %s", hipGetErrorString(ce));
+    HIPCHK(ctx, hipGraphInstantiate(&r.gexec, r.graph, nullptr, nullptr, 0));
+    return OFM_OK;
+}
+
+// Drop the tiles of finished samples from the work list once they are more
+// than a tenth of it.  The launch index is mapped to work items in
+// contiguous ranges per XCD, so tiles that exit at once would otherwise
+// leave some XCDs idle while others carry the live samples; the graph is
+// captured again for the shorter grid.  Results do not depend on the tile
+// order (each cell's arithmetic and each sample's reduction order are fixed).
+static int run_compact(ofm_run& r)
+{
+    int64_t live = 0;
+    for (size_t i = 0; i < r.mem.size(); ++i)
+        if (!r.host_state[i].done) live += r.desc[i].ntiles;
+    if (live == 0 || (double)live > 0.9 * (double)r.la.n_work) return OFM_OK;
+    std::vector<WorkItem> work;
+    work.reserve(live);
+    for (int i : r.order)
+        if (!r.host_state[i].done)
+            for (int t = 0; t < r.desc[i].ntiles; ++t) work.push_back(WorkItem{ i, t });
+    ofm_ctx* ctx = r.ctx;
+    HIPCHK(ctx, hipMemcpyAsync(r.d_work, work.data(), sizeof(WorkItem) * work.size(), hipMemcpyHostToDevice,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    r.la.n_work = (int)work.size();
+    return r.eager ? OFM_OK : run_capture(r);
 }
 
 // Set up a run of r.mem: descriptors, work list, (init: Q_0 from the
@@ -235,12 +288,12 @@ static int run_begin(ofm_ctx* ctx, ofm_run& r, bool init, int64_t dts_len, hipSt
         tiles += d.ntiles;
     }
     // work list: larger samples first, tiles of a sample contiguous
-    std::vector<int> order(ns);
-    for (int i = 0; i < ns; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return mem[a].spec.n > mem[b].spec.n; });
+    r.order.resize(ns);
+    for (int i = 0; i < ns; ++i) r.order[i] = i;
+    std::stable_sort(r.order.begin(), r.order.end(), [&](int a, int b) { return mem[a].spec.n > mem[b].spec.n; });
     std::vector<WorkItem> work;
     work.reserve(tiles);
-    for (int i : order)
+    for (int i : r.order)
         for (int t = 0; t < r.desc[i].ntiles; ++t) work.push_back(WorkItem{ i, t });
 
     const size_t o_desc = 0;
@@ -271,7 +324,7 @@ static int run_begin(ofm_ctx* ctx, ofm_run& r, bool init, int64_t dts_len, hipSt
     r.d_desc = (SampleDesc*)(meta + o_desc);
     r.d_state = (SampleState*)(meta + o_state);
     r.d_part = (TilePartial*)(meta + o_part);
-    WorkItem* d_work = (WorkItem*)(meta + o_work);
+    WorkItem* d_work = r.d_work = (WorkItem*)(meta + o_work);
     r.d_dt = dts_len > 0 ? (double*)(meta + o_dt) : nullptr;
 
     std::vector<SampleState> st0(ns);
@@ -346,22 +399,7 @@ static int run_begin(ofm_ctx* ctx, ofm_run& r, bool init, int64_t dts_len, hipSt
     r.live_cells = 0.0;
     for (int i = 0; i < ns; ++i) r.live_cells += (double)cells_of(mem[i].spec);
     r.state.assign(st0.begin(), st0.end());
-    if (!r.eager) {
-        HIPCHK(ctx, hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-        int rc = OFM_OK;
-        for (int g = 0; g < r.K && rc == OFM_OK; ++g)
-            for (int stg = 0; stg < 3 && rc == OFM_OK; ++stg) {
-                la.src = (g + stg) & 1;     // replayed at even step indices only
-                hipError_t le = launch_stage(prec, nd, tc.tx, tc.ty, la, stg, stream);
-                if (le == hipSuccess && stg == 2)
-                    le = launch_finalize(r.d_desc, r.d_state, r.d_part, ns, 0, r.d_dt, dts_len, stream);
-                if (le != hipSuccess) rc = fail(ctx, OFM_EHIP, "launch failed: %s", hipGetErrorString(le));
-            }
-        hipError_t ce = hipStreamEndCapture(stream, &r.graph);
-        if (rc) return rc;
-        if (ce != hipSuccess) return fail(ctx, OFM_EHIP, "graph capture failed: %s", hipGetErrorString(ce));
-        HIPCHK(ctx, hipGraphInstantiate(&r.gexec, r.graph, nullptr, nullptr, 0));
-    }
+    if (!r.eager) return run_capture(r);
     return OFM_OK;
 }
 
@@ -431,6 +469,7 @@ static int run_advance(ofm_run& r, int64_t max_steps)
         }
         r.state.assign(r.host_state, r.host_state + ns);
         if (all) { r.finished = true; break; }
+        if ((rc = run_compact(r)) != OFM_OK) { result = rc; break; }
         if (r.taken > r.cap + 2 * r.K) { result = fail(ctx, OFM_EHIP, "samples did not finish within the step cap"); break; }
         if (r.taken - start >= max_steps) break;
     }

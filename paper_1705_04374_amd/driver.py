@@ -130,8 +130,10 @@ def solve_many(ctx: capi.Context, specs: list, bubbles: list, max_batch_bytes: f
                 if time.perf_counter() - last >= progress_seconds:
                     st = run.status()
                     live = [q["t"] for q in st["qoi"] if q["status"] == SAMPLE_OK]
-                    log("    batch of %d (n = %s): %d steps, slowest t = %.3e" % (
-                        len(batch), sorted({specs[i].n for i in batch}), st["steps"], min(live) if live else 0.0))
+                    cs = sum(float(specs[i].n) ** specs[i].ndim * q["steps"] for i, q in zip(batch, st["qoi"]))
+                    log("    batch of %d (n = %s): %d steps, slowest t = %.3e, %.3g cell-steps/s so far" % (
+                        len(batch), sorted({specs[i].n for i in batch}), st["steps"], min(live) if live else 0.0,
+                        cs / max(st["step_s"], 1e-9)))
                     last = time.perf_counter()
             qs = run.status()["qoi"]
         finally:
@@ -139,6 +141,8 @@ def solve_many(ctx: capi.Context, specs: list, bubbles: list, max_batch_bytes: f
         wall = time.perf_counter() - t0
         work = [float(specs[i].n) ** specs[i].ndim * max(q["steps"], 1) for i, q in zip(batch, qs)]
         tot = sum(work)
+        log("    batch of %d done: %.1f s, %.3g cell-steps/s, %d failed" % (
+            len(batch), wall, tot / wall, sum(q["status"] != SAMPLE_OK for q in qs)))
         for i, q, w in zip(batch, qs, work):
             out[i] = q
             secs[i] = wall * w / tot
@@ -348,6 +352,7 @@ class OFMLMC:
             M, flag = self.allocate(res["sigma_t2"], W, tau)
             M = [min(m, c) if c else m for m, c in zip(M, cap)]
             target = [max(m, c) for m, c in zip(M, self.count)]
+            log("  next counts %s (allocation flag %d)" % (target, flag))
             if target == self.count:
                 break
         out = dict(history[-1])
