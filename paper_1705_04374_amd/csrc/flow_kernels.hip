@@ -172,31 +172,46 @@ __device__ __forceinline__ void weno5_cell(T a, T b, T c, T d, T e, T eps_s, T& 
 // both edges (first order for that variable alone, so that a decision taken
 // on round-off moves the edges by round-off).  If then either edge state has
 // (Gamma+1) p + Pi <= 0, the whole cell is first order.
+//
+// The gas's partial density and volume fraction are exactly zero in pure
+// water, i.e. in most of a cloud's domain for the whole run.  WENO5 of a
+// constant stencil returns the constant exactly, so where the stencils of a
+// whole wavefront are constant in those two variables their reconstruction
+// is skipped (same values, bit for bit).
 template <typename T, int ND>
 __device__ __forceinline__ void cell_edges(const Phys<T>& ph, const T (&s)[5][4 + ND],
                                            T (&lo)[4 + ND], T (&hi)[4 + ND])
 {
     constexpr int NV = 4 + ND;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) weno5_cell<T>(s[0][v], s[1][v], s[2][v], s[3][v], s[4][v], ph.eps, lo[v], hi[v]);
+    for (int v = 0; v < NV; ++v) {
+        if (v == 1 || v == NV - 1) {
+            // constant stencil across the wavefront: the edges are the cell
+            // value, which every check below would keep as well
+            const bool flat = s[0][v] == s[2][v] && s[1][v] == s[2][v] && s[3][v] == s[2][v] && s[4][v] == s[2][v];
+            if (__all(flat)) {
+                lo[v] = s[2][v];
+                hi[v] = s[2][v];
+                continue;
+            }
+        }
+        weno5_cell<T>(s[0][v], s[1][v], s[2][v], s[3][v], s[4][v], ph.eps, lo[v], hi[v]);
+        if (v < 2) {
+            T big = v == 0 ? ph.rho1 : ph.rho2;
 #pragma unroll
-    for (int v = 0; v < 2; ++v) {
-        T big = v == 0 ? ph.rho1 : ph.rho2;
-#pragma unroll
-        for (int k = 0; k < 5; ++k) big = fmax(big, fabs(s[k][v]));
-        const T tol = -Num<T>::round_tol * big;
-        const T mid = (T(12) * s[2][v] - lo[v] - hi[v]) * T(0.1);
-        const bool keep = (lo[v] >= tol) && (hi[v] >= tol) && (mid >= tol);
-        lo[v] = keep ? lo[v] : s[2][v];
-        hi[v] = keep ? hi[v] : s[2][v];
-    }
-    {
-        constexpr int v = 3 + ND;
-        const T lb = -Num<T>::round_tol, ub = T(1) + Num<T>::round_tol;
-        const T mid = (T(12) * s[2][v] - lo[v] - hi[v]) * T(0.1);
-        const bool keep = (lo[v] >= lb) && (lo[v] <= ub) && (hi[v] >= lb) && (hi[v] <= ub) && (mid >= lb) && (mid <= ub);
-        lo[v] = keep ? lo[v] : s[2][v];
-        hi[v] = keep ? hi[v] : s[2][v];
+            for (int k = 0; k < 5; ++k) big = fmax(big, fabs(s[k][v]));
+            const T tol = -Num<T>::round_tol * big;
+            const T mid = (T(12) * s[2][v] - lo[v] - hi[v]) * T(0.1);
+            const bool keep = (lo[v] >= tol) && (hi[v] >= tol) && (mid >= tol);
+            lo[v] = keep ? lo[v] : s[2][v];
+            hi[v] = keep ? hi[v] : s[2][v];
+        } else if (v == NV - 1) {
+            const T lb = -Num<T>::round_tol, ub = T(1) + Num<T>::round_tol;
+            const T mid = (T(12) * s[2][v] - lo[v] - hi[v]) * T(0.1);
+            const bool keep = (lo[v] >= lb) && (lo[v] <= ub) && (hi[v] >= lb) && (hi[v] <= ub) && (mid >= lb) && (mid <= ub);
+            lo[v] = keep ? lo[v] : s[2][v];
+            hi[v] = keep ? hi[v] : s[2][v];
+        }
     }
     const T cl = (ph.gamma(lo[3 + ND]) + T(1)) * lo[2 + ND] + ph.pinf(lo[3 + ND]);
     const T ch = (ph.gamma(hi[3 + ND]) + T(1)) * hi[2 + ND] + ph.pinf(hi[3 + ND]);

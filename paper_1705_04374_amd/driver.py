@@ -497,6 +497,29 @@ def _run_workload(a, w, ctx, cloud, T, seed, deadline, log) -> dict:
         out["ofmlmc"] = mc.evaluate(W)
         out["mlmc"] = mc.evaluate(W, classical=True)
         out["cost_seconds"] = sum(mc.time)
+        # the same solves one at a time (no batching, a graph per solve), in
+        # FP32 and in plain FP64: measured on one cloud per level, times the
+        # number of solves at that level
+        solves = {n: 0 for n in w["levels"]}
+        for k, m in enumerate(w["counts"]):
+            solves[w["levels"][k]] += m
+            if k >= 1:
+                solves[w["levels"][k - 1]] += m
+        single = {}
+        b = capi.ofm_sample_cloud(cloud, seed, 0, 0)
+        for prec in ("f32", "f64"):
+            for n in w["levels"]:
+                t0 = time.perf_counter()
+                q = capi.ofm_solve(ctx, mc.spec(n, prec), b)
+                single["%s_%d" % (prec, n)] = dict(seconds=time.perf_counter() - t0, steps=q["steps"],
+                                                    status=q["status"])
+                log("  single %s %d^3: %.2f s, %d steps" % (prec, n, single["%s_%d" % (prec, n)]["seconds"],
+                                                            q["steps"]))
+        out["solves_per_level"] = solves
+        out["single_solves"] = single
+        for prec in ("f32", "f64"):
+            out["sequential_%s_seconds" % prec] = sum(solves[n] * single["%s_%d" % (prec, n)]["seconds"]
+                                                      for n in w["levels"])
     elif a.workload == "surrogate":
         cfg = solver_config(w["cloud"], w["n_train"])
         sur, info = train_level(ctx, cloud, cfg, w["n_train"], w["count_train"], T, seed, w["precision"],
