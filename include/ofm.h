@@ -101,9 +101,18 @@ typedef struct {
     int64_t max_steps;   /* step cap (status OFM_SAMPLE_MAX_STEPS) */
 } ofm_solve_spec;
 
-/* Quantity of interest of one solve (Sec. 3.3): maximum cell pressure over
- * cells and time levels n = 0..steps; ties to the smallest flat cell index
- * (k n + j) n + i, then to the earliest level. */
+/* Quantities of interest of one solve (Sec. 3.3), over the time levels
+ * n = 0..steps:
+ *   p_max: maximum cell pressure over cells and levels; ties to the smallest
+ *     flat cell index (k n + j) n + i, then to the earliest level;
+ *   p_sensor: maximum over levels of the pressure sensor of eq. (sensor), the
+ *     mean pressure over the cells whose centres lie within
+ *     max(R_c / 40, 1.01 half cell diagonals) of the cloud centre (the paper's
+ *     0.5 mm ball in its 20 mm cloud); earliest level on ties;
+ *   gas_min: minimum over levels of the gas-fraction sensor, the mean a2 over
+ *     the cells whose centres lie within R_c of the cloud centre;
+ *   c_max: maximum sound speed over cells and levels;
+ *   peak_distance: distance of the p_max cell centre from the cloud centre. */
 typedef struct {
     double p_max;
     double x[3];         /* centre of the argmax cell (unused axes 0) */
@@ -113,6 +122,10 @@ typedef struct {
     int64_t steps;       /* steps taken */
     int32_t status;      /* OFM_SAMPLE_* */
     int32_t reserved;
+    double p_sensor, t_p_sensor;
+    double gas_min, t_gas_min;
+    double c_max;
+    double peak_distance;
 } ofm_qoi;
 
 /* Random cloud geometry (Sec. 3, 3.1): n_bubbles centres uniform in the

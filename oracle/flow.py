@@ -52,6 +52,8 @@ class Qoi(C.Structure):
     _fields_ = [
         ("p_max", C.c_double), ("x", C.c_double * 3), ("t_at_max", C.c_double), ("t", C.c_double),
         ("argmax", C.c_int64), ("steps", C.c_int64), ("status", C.c_int32), ("pad", C.c_int32),
+        ("p_sensor", C.c_double), ("t_p_sensor", C.c_double), ("gas_min", C.c_double),
+        ("t_gas_min", C.c_double), ("c_max", C.c_double), ("peak_distance", C.c_double),
     ]
 
 
@@ -59,6 +61,8 @@ class Reduction(C.Structure):
     _fields_ = [
         ("s_max", C.c_double), ("p_max", C.c_double), ("argmax", C.c_int64),
         ("n_nonfinite", C.c_int64), ("n_negc2", C.c_int64),
+        ("c_max", C.c_double), ("p_ball", C.c_double), ("a2_ball", C.c_double),
+        ("n_ball_p", C.c_int64), ("n_ball_a", C.c_int64),
     ]
 
 
@@ -203,7 +207,8 @@ def reduce(cfg: dict, U: np.ndarray, box=None) -> dict:
     r = Reduction()
     lib().orc_reduce(C.byref(s), C.byref(_box(cfg, box)), _ptr(U), C.byref(r))
     return dict(s_max=r.s_max, p_max=r.p_max, argmax=r.argmax,
-                n_nonfinite=r.n_nonfinite, n_negc2=r.n_negc2)
+                n_nonfinite=r.n_nonfinite, n_negc2=r.n_negc2, c_max=r.c_max, p_ball=r.p_ball,
+                a2_ball=r.a2_ball, n_ball_p=r.n_ball_p, n_ball_a=r.n_ball_a)
 
 
 def initial_reduction(cfg: dict, bubbles: np.ndarray) -> dict:
@@ -212,7 +217,8 @@ def initial_reduction(cfg: dict, bubbles: np.ndarray) -> dict:
     r = Reduction()
     lib().orc_initial_reduction(C.byref(s), _ptr(bub), bub.shape[0], C.byref(r))
     return dict(s_max=r.s_max, p_max=r.p_max, argmax=r.argmax,
-                n_nonfinite=r.n_nonfinite, n_negc2=r.n_negc2)
+                n_nonfinite=r.n_nonfinite, n_negc2=r.n_negc2, c_max=r.c_max, p_ball=r.p_ball,
+                a2_ball=r.a2_ball, n_ball_p=r.n_ball_p, n_ball_a=r.n_ball_a)
 
 
 def run_steps(cfg: dict, U: np.ndarray, n_steps: int):
@@ -252,7 +258,8 @@ def solve(cfg: dict, bubbles: np.ndarray, t_end: float = 0.0, n_steps: int = 0,
     q = Qoi()
     lib().orc_solve(C.byref(s), _ptr(U), t_end, n_steps, max_steps, C.byref(q))
     return dict(p_max=q.p_max, x=tuple(q.x), t_at_max=q.t_at_max, t=q.t, argmax=q.argmax,
-                steps=q.steps, status=q.status, U=U)
+                steps=q.steps, status=q.status, p_sensor=q.p_sensor, t_p_sensor=q.t_p_sensor,
+                gas_min=q.gas_min, t_gas_min=q.t_gas_min, c_max=q.c_max, peak_distance=q.peak_distance, U=U)
 
 
 def weno5_right_edge(a, b, c, d, e, eps=1e-6) -> float:

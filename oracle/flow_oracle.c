@@ -90,6 +90,13 @@ typedef struct {
     int64_t steps;
     int32_t status;    /* 0 ok, 1 non-finite, 2 c^2 <= 0, 3 step cap */
     int32_t pad;
+    /* the paper's other quantities of interest (Sec. 3.3) */
+    double p_sensor;   /* max over time levels of the pressure sensor, eq. (sensor) */
+    double t_p_sensor; /* its time */
+    double gas_min;    /* min over time levels of the cloud gas-fraction sensor */
+    double t_gas_min;  /* its time */
+    double c_max;      /* max over time levels and cells of the sound speed */
+    double peak_distance; /* distance of the p_max cell centre from the cloud centre */
 } orc_qoi;
 
 typedef struct {
@@ -98,6 +105,10 @@ typedef struct {
     int64_t argmax;
     int64_t n_nonfinite;
     int64_t n_negc2;
+    double c_max;      /* max_cells c */
+    double p_ball;     /* sum of p over the cells of the pressure sensor's ball */
+    double a2_ball;    /* sum of a2 over the cells of the gas sensor's ball */
+    int64_t n_ball_p, n_ball_a;   /* their cell counts */
 } orc_reduction;
 
 /* ------------------------------------------------------------------ */
@@ -501,6 +512,32 @@ void orc_step(const orc_spec* s, const orc_box* box, double* U, double dt)
 /* CFL / QoI reduction                                                 */
 /* ------------------------------------------------------------------ */
 
+/* Sensors (Sec. 3.3, eq. (sensor)): averages over the cells whose centres
+ * lie in a ball around the cloud centre (midpoint rule for the ball
+ * integral).  Reading: the pressure sensor's radius is the paper's 0.5 mm
+ * against its 20 mm cloud, R_c / 40, but at least 1.01 half cell diagonals
+ * (so that coarse grids average the 2^d cells around the centre instead of
+ * none); the gas-fraction sensor's ball is the cloud's (radius R_c: the
+ * paper's sensor containing the entire cloud). */
+static double sensor_r2_p(const orc_spec* s)
+{
+    double h = 1.0 / (double)s->n;
+    double r = s->cloud_radius / 40.0;
+    double hd = 1.01 * 0.5 * h * sqrt((double)s->ndim);
+    if (hd > r) r = hd;
+    return r * r;
+}
+
+static double centre_dist2(const orc_spec* s, int64_t i, int64_t j, int64_t k)
+{
+    double N = (double)s->n;
+    double dx = ((double)i + 0.5) / N - s->center[0];
+    double d2 = dx * dx;
+    if (s->ndim > 1) { double dy = ((double)j + 0.5) / N - s->center[1]; d2 = d2 + dy * dy; }
+    if (s->ndim > 2) { double dz = ((double)k + 0.5) / N - s->center[2]; d2 = d2 + dz * dz; }
+    return d2;
+}
+
 void orc_reduce(const orc_spec* s, const orc_box* box, const double* U, orc_reduction* r)
 {
     grid g;
@@ -513,6 +550,12 @@ void orc_reduce(const orc_spec* s, const orc_box* box, const double* U, orc_redu
     r->argmax = -1;
     r->n_nonfinite = 0;
     r->n_negc2 = 0;
+    r->c_max = 0.0;
+    r->p_ball = 0.0;
+    r->a2_ball = 0.0;
+    r->n_ball_p = 0;
+    r->n_ball_a = 0;
+    const double r2p = sensor_r2_p(s), r2a = s->cloud_radius * s->cloud_radius;
     for (int k = 0; k < g.box.len[2]; ++k)
     for (int j = 0; j < g.box.len[1]; ++j)
     for (int i = 0; i < g.box.len[0]; ++i) {
@@ -535,6 +578,10 @@ void orc_reduce(const orc_spec* s, const orc_box* box, const double* U, orc_redu
             double sp = fabs(w[2 + m]) + cs;
             if (sp > r->s_max) r->s_max = sp;
         }
+        if (cs > r->c_max) r->c_max = cs;
+        double d2 = centre_dist2(s, i + g.box.lo[0], j + g.box.lo[1], k + g.box.lo[2]);
+        if (d2 <= r2p) { r->p_ball += p; r->n_ball_p++; }
+        if (d2 <= r2a) { r->a2_ball += w[3 + d]; r->n_ball_a++; }
         int64_t gi = ((int64_t)(k + g.box.lo[2]) * N + (j + g.box.lo[1])) * N + (i + g.box.lo[0]);
         if (p > r->p_max || (p == r->p_max && gi < r->argmax)) {
             r->p_max = p;
@@ -672,6 +719,11 @@ void orc_solve(const orc_spec* s, double* U, double t_end, int64_t n_steps,
     q->argmax = r.argmax;
     q->t_at_max = 0.0;
     q->pad = 0;
+    q->p_sensor = r.n_ball_p > 0 ? r.p_ball / (double)r.n_ball_p : 0.0;
+    q->t_p_sensor = 0.0;
+    q->gas_min = r.n_ball_a > 0 ? r.a2_ball / (double)r.n_ball_a : 0.0;
+    q->t_gas_min = 0.0;
+    q->c_max = r.c_max;
     if (r.n_nonfinite > 0) q->status = 1;
     else if (r.n_negc2 > 0) q->status = 2;
     double t = 0.0;
@@ -692,9 +744,19 @@ void orc_solve(const orc_spec* s, double* U, double t_end, int64_t n_steps,
             q->argmax = r.argmax;
             q->t_at_max = t;
         }
+        double ps = r.n_ball_p > 0 ? r.p_ball / (double)r.n_ball_p : 0.0;
+        double gs = r.n_ball_a > 0 ? r.a2_ball / (double)r.n_ball_a : 0.0;
+        if (ps > q->p_sensor) { q->p_sensor = ps; q->t_p_sensor = t; }
+        if (gs < q->gas_min) { q->gas_min = gs; q->t_gas_min = t; }
+        if (r.c_max > q->c_max) q->c_max = r.c_max;
     }
     q->t = t;
     cell_centre(s, q->argmax < 0 ? 0 : q->argmax, q->x);
+    {
+        double dd = 0.0;
+        for (int a = 0; a < s->ndim; ++a) dd = dd + (q->x[a] - s->center[a]) * (q->x[a] - s->center[a]);
+        q->peak_distance = sqrt(dd);
+    }
 }
 
 /* Run exactly n_steps steps on the whole domain and report the time step
@@ -737,6 +799,11 @@ void orc_initial_reduction(const orc_spec* s, const double* bubbles, int32_t nb,
     r->argmax = -1;
     r->n_nonfinite = 0;
     r->n_negc2 = 0;
+    r->c_max = 0.0;
+    r->p_ball = 0.0;
+    r->a2_ball = 0.0;
+    r->n_ball_p = 0;
+    r->n_ball_a = 0;
     for (int k = 0; k < nz; ++k) {
         orc_box b = { { 0, 0, k }, { N, ny, 1 } };
         orc_reduction rs;
@@ -749,6 +816,11 @@ void orc_initial_reduction(const orc_spec* s, const double* bubbles, int32_t nb,
         }
         r->n_nonfinite += rs.n_nonfinite;
         r->n_negc2 += rs.n_negc2;
+        if (rs.c_max > r->c_max) r->c_max = rs.c_max;
+        r->p_ball += rs.p_ball;
+        r->a2_ball += rs.a2_ball;
+        r->n_ball_p += rs.n_ball_p;
+        r->n_ball_a += rs.n_ball_a;
     }
     free(slab);
 }

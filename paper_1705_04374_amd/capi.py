@@ -61,11 +61,15 @@ class Qoi(C.Structure):
     _fields_ = [
         ("p_max", C.c_double), ("x", C.c_double * 3), ("t_at_max", C.c_double), ("t", C.c_double),
         ("argmax", C.c_int64), ("steps", C.c_int64), ("status", C.c_int32), ("reserved", C.c_int32),
+        ("p_sensor", C.c_double), ("t_p_sensor", C.c_double), ("gas_min", C.c_double), ("t_gas_min", C.c_double),
+        ("c_max", C.c_double), ("peak_distance", C.c_double),
     ]
 
     def as_dict(self) -> dict:
         return dict(p_max=self.p_max, x=tuple(self.x), t_at_max=self.t_at_max, t=self.t, argmax=self.argmax,
-                    steps=self.steps, status=self.status)
+                    steps=self.steps, status=self.status, p_sensor=self.p_sensor, t_p_sensor=self.t_p_sensor,
+                    gas_min=self.gas_min, t_gas_min=self.t_gas_min, c_max=self.c_max,
+                    peak_distance=self.peak_distance)
 
 
 class CloudSpec(C.Structure):

@@ -285,6 +285,16 @@ static int run_begin(ofm_ctx* ctx, ofm_run& r, bool init, int64_t dts_len, hipSt
         d.t_end = s.n_steps > 0 ? INFINITY : s.t_end;
         d.n_steps = s.n_steps;
         d.max_steps = s.max_steps;
+        // sensors (ofm_qoi): pressure ball of radius max(R_c / 40, 1.01 half
+        // cell diagonals), gas-fraction ball of radius R_c, at the cloud centre
+        for (int a = 0; a < 3; ++a) d.centre[a] = s.center[a];
+        {
+            double rp = s.cloud_radius / 40.0;
+            const double hd = 1.01 * 0.5 * d.h * sqrt((double)s.ndim);
+            if (hd > rp) rp = hd;
+            d.r2_p = rp * rp;
+            d.r2_a = s.cloud_radius * s.cloud_radius;
+        }
         tiles += d.ntiles;
     }
     // work list: larger samples first, tiles of a sample contiguous
@@ -522,6 +532,14 @@ static void to_qoi(const ofm_solve_spec& s, const SampleState& st, ofm_qoi* q)
     q->x[0] = ((double)(a % n) + 0.5) / (double)n;
     if (s.ndim > 1) q->x[1] = ((double)((a / n) % n) + 0.5) / (double)n;
     if (s.ndim > 2) q->x[2] = ((double)(a / (n * n)) + 0.5) / (double)n;
+    q->p_sensor = st.p_sensor;
+    q->t_p_sensor = st.t_p_sensor;
+    q->gas_min = st.gas_min;
+    q->t_gas_min = st.t_gas_min;
+    q->c_max = st.c_max;
+    double dd = 0.0;
+    for (int k = 0; k < s.ndim; ++k) dd = dd + (q->x[k] - s.center[k]) * (q->x[k] - s.center[k]);
+    q->peak_distance = sqrt(dd);
 }
 
 }  // namespace ofm

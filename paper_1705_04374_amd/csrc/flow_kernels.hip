@@ -302,12 +302,18 @@ __device__ __forceinline__ T k_coef(const Phys<T>& ph, T a2, T p)
     return (a == T(0) || a == T(1) || den == T(0)) ? T(0) : k;
 }
 
-// Running reduction of one thread (CFL speed, QoI, failure counters).
+// Running reduction of one thread (CFL speed, QoIs, failure counters).
 struct Red {
     double s_max, p_max;
     int64_t argmax;
     int n_nf, n_c2;
-    __device__ __forceinline__ void init() { s_max = 0.0; p_max = -INFINITY; argmax = INT64_MAX; n_nf = 0; n_c2 = 0; }
+    double c_max, p_ball, a_ball;   // sound speed; sums over the sensors' balls
+    int n_p, n_a;                   // cells in the balls
+    __device__ __forceinline__ void init()
+    {
+        s_max = 0.0; p_max = -INFINITY; argmax = INT64_MAX; n_nf = 0; n_c2 = 0;
+        c_max = 0.0; p_ball = 0.0; a_ball = 0.0; n_p = 0; n_a = 0;
+    }
     __device__ __forceinline__ void take(double s, double p, int64_t idx)
     {
         s_max = fmax(s_max, s);
@@ -319,12 +325,33 @@ struct Red {
         if (o.p_max > p_max || (o.p_max == p_max && o.argmax < argmax)) { p_max = o.p_max; argmax = o.argmax; }
         n_nf += o.n_nf;
         n_c2 += o.n_c2;
+        c_max = fmax(c_max, o.c_max);
+        p_ball += o.p_ball;
+        a_ball += o.a_ball;
+        n_p += o.n_p;
+        n_a += o.n_a;
     }
 };
 
-// Accumulate one cell of a new state into the reduction (all in double).
+// Squared distance of a cell centre from the cloud centre, in the order
+// x, then y, then z, without contraction (the sensors' ball membership).
+__device__ __forceinline__ double axis_dist2(double centre, int i, double n)
+{
+#pragma clang fp contract(off)
+    const double dx = ((double)i + 0.5) / n - centre;
+    return dx * dx;
+}
+__device__ __forceinline__ double add_dist2(double a, double b)
+{
+#pragma clang fp contract(off)
+    return a + b;
+}
+
+// Accumulate one cell of a new state into the reduction (all in double);
+// d2: the cell centre's squared distance from the cloud centre.
 template <typename T, int ND>
-__device__ __forceinline__ void reduce_cell(const PhysD& ph, const T (&q)[4 + ND], int64_t idx, Red& r)
+__device__ __forceinline__ void reduce_cell(const PhysD& ph, const SampleDesc& d, const T (&q)[4 + ND], int64_t idx,
+                                            double d2, Red& r)
 {
     constexpr int NV = 4 + ND;
     bool finite = true;
@@ -349,16 +376,18 @@ __device__ __forceinline__ void reduce_cell(const PhysD& ph, const T (&q)[4 + ND
     if (!finite) { r.n_nf++; return; }
     double c2 = ((G + 1.0) * p + P) * iG * irho;
     if (!(rho > 0.0) || !(c2 > 0.0)) { r.n_c2++; return; }
-    r.take(umax + sqrt(c2), p, idx);
+    const double cs = sqrt(c2);
+    r.take(umax + cs, p, idx);
+    r.c_max = fmax(r.c_max, cs);
+    if (d2 <= d.r2_p) { r.p_ball += p; r.n_p++; }
+    if (d2 <= d.r2_a) { r.a_ball += a2; r.n_a++; }
 }
 
 // Workgroup-wide merge of the thread reductions; thread 0 writes the tile.
-template <int NT>
-__device__ __forceinline__ void write_partial(Red r, TilePartial* out)
+// Butterfly merge of the 64 lanes' reductions (fixed order: every lane ends
+// with the same result).
+__device__ __forceinline__ void wave_merge(Red& r)
 {
-    __shared__ double s_s[NT / 64], s_p[NT / 64];
-    __shared__ int64_t s_a[NT / 64];
-    __shared__ int s_n[NT / 64], s_c[NT / 64];
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         Red o;
@@ -367,24 +396,48 @@ __device__ __forceinline__ void write_partial(Red r, TilePartial* out)
         o.argmax = __shfl_xor(r.argmax, off, 64);
         o.n_nf = __shfl_xor(r.n_nf, off, 64);
         o.n_c2 = __shfl_xor(r.n_c2, off, 64);
+        o.c_max = __shfl_xor(r.c_max, off, 64);
+        o.p_ball = __shfl_xor(r.p_ball, off, 64);
+        o.a_ball = __shfl_xor(r.a_ball, off, 64);
+        o.n_p = __shfl_xor(r.n_p, off, 64);
+        o.n_a = __shfl_xor(r.n_a, off, 64);
         r.merge(o);
     }
+}
+
+// Workgroup-wide merge of the thread reductions (waves in order, through
+// LDS); thread 0 returns the result.
+template <int NT>
+__device__ __forceinline__ Red block_merge(Red r)
+{
+    __shared__ Red s_r[NT / 64];
+    wave_merge(r);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) { s_s[wave] = r.s_max; s_p[wave] = r.p_max; s_a[wave] = r.argmax; s_n[wave] = r.n_nf; s_c[wave] = r.n_c2; }
+    if (lane == 0) s_r[wave] = r;
     __syncthreads();
+    Red t;
+    t.init();
+    if (threadIdx.x == 0)
+        for (int w = 0; w < NT / 64; ++w) t.merge(s_r[w]);
+    return t;
+}
+
+// Workgroup-wide merge of the thread reductions; thread 0 writes the tile.
+template <int NT>
+__device__ __forceinline__ void write_partial(Red r, TilePartial* out)
+{
+    const Red t = block_merge<NT>(r);
     if (threadIdx.x == 0) {
-        Red t;
-        t.init();
-        for (int w = 0; w < NT / 64; ++w) {
-            Red o;
-            o.s_max = s_s[w]; o.p_max = s_p[w]; o.argmax = s_a[w]; o.n_nf = s_n[w]; o.n_c2 = s_c[w];
-            t.merge(o);
-        }
         out->s_max = t.s_max;
         out->p_max = t.p_max;
         out->argmax = t.argmax;
         out->n_nonfinite = t.n_nf;
         out->n_negc2 = t.n_c2;
+        out->c_max = t.c_max;
+        out->p_ball = t.p_ball;
+        out->a2_ball = t.a_ball;
+        out->n_ball_p = t.n_p;
+        out->n_ball_a = t.n_a;
     }
 }
 
@@ -411,13 +464,16 @@ constexpr int round_up64(int x) { return (x + 63) / 64 * 64; }
 template <int TX, int TY> constexpr int stage_threads() { return round_up64(TX * TY); }
 
 // Occupancy target of the stage kernel: three wavefronts per SIMD for the
-// float kernels (at most 168 VGPRs), one for double.
+// float kernels (at most 168 VGPRs), one for double (whose LDS tile allows no
+// more).
 template <typename T> constexpr int stage_waves_per_eu() { return sizeof(T) == 4 ? 3 : 1; }
 
-template <typename T, int ND, int TX, int TY>
+// RK stage STAGE = 0, 1, 2 (compiled separately: only the last carries the
+// reduction, only the first skips dU).
+template <typename T, int ND, int TX, int TY, int STAGE>
 __global__ void __launch_bounds__((stage_threads<TX, TY>()))
 __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<T>())))
-stage_kernel(LaunchArgs a, int stage)
+stage_kernel(LaunchArgs a)
 {
     constexpr int NV = 4 + ND;
     constexpr int NT = stage_threads<TX, TY>();
@@ -469,6 +525,7 @@ stage_kernel(LaunchArgs a, int stage)
     T* __restrict__ du = (T*)d.du;
     const T dt = (T)st->dt;
     const T ih = (T)(1.0 / d.h);
+    constexpr int stage = STAGE;
     const T rkA = (T)c_rk_a[stage], rkB = (T)c_rk_b[stage];
     const int bc = a.bc;
 
@@ -563,19 +620,25 @@ stage_kernel(LaunchArgs a, int stage)
         L[NV - 1] += sk * divu;              // R_7 = (a2 + K) div u
         L[NV - 2] -= ph.pinf(sk) * divu;     // Et = E - Pi(a2): -Pi(a2 + K) div u
     };
+    // squared distances from the cloud centre (sensors): this thread's x-y
+    // part, completed per plane in 3-D
+    const double n_d = (double)n;
+    double dxy2 = axis_dist2(d.centre[0], gx, n_d);
+    if (ND >= 2) dxy2 = add_dist2(dxy2, axis_dist2(d.centre[1], gy, n_d));
+
     // the low-storage RK stage of one cell, given its U and dU
-    auto update = [&](int64_t idx, const T (&L)[NV], const T (&uo)[NV], const T (&duo)[NV]) {
+    auto update = [&](int64_t idx, const T (&L)[NV], const T (&uo)[NV], const T (&duo)[NV], double d2) {
         T qn[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const int64_t o = v * ncell + idx;
             T dv = dt * L[v];
-            if (stage > 0) dv += rkA * duo[v];
-            if (stage < 2) du[o] = dv;
+            if constexpr (stage > 0) dv += rkA * duo[v];
+            if constexpr (stage < 2) du[o] = dv;
             qn[v] = uo[v] + rkB * dv;
             ub[o] = qn[v];
         }
-        if (stage == 2) reduce_cell<T, ND>(a.ph, qn, idx, red);
+        if constexpr (stage == 2) reduce_cell<T, ND>(a.ph, d, qn, idx, d2, red);
     };
 
     if constexpr (ND <= 2) {
@@ -595,7 +658,7 @@ stage_kernel(LaunchArgs a, int stage)
                 uo[v] = ua[v * ncell + idx];
                 duo[v] = stage > 0 ? du[v * ncell + idx] : T(0);
             }
-            update(idx, L, uo, duo);
+            update(idx, L, uo, duo, dxy2);
         }
     } else {
         // z: each thread keeps the primitives of its own column, planes
@@ -620,22 +683,27 @@ stage_kernel(LaunchArgs a, int stage)
             // p+3 and this cell's U and dU
             const int64_t inext = (int64_t)bc_map(p + 3, n, bc) * plane + col;
             const int64_t icell = (int64_t)p * plane + col;
+            // (in double, U and dU are loaded after the x-y work instead: 28
+            // more registers across it would halve the occupancy)
+            constexpr bool early = sizeof(T) == 4;
             T qn[NV], uo[NV], duo[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) qn[v] = ua[v * ncell + inext];
-            if (xy_work) {
+            auto load_cell = [&]() {
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
                     uo[v] = ua[v * ncell + icell];
                     duo[v] = stage > 0 ? du[v * ncell + icell] : T(0);
                 }
-            }
+            };
+#pragma unroll
+            for (int v = 0; v < NV; ++v) qn[v] = ua[v * ncell + inext];
+            if (early && xy_work) load_cell();
             T xy[NV + 1];
             if (xy_work) {
                 __syncthreads();
                 load_plane(p);
                 __syncthreads();
                 plane_xy(xy);
+                if (!early) load_cell();
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k)
@@ -654,7 +722,7 @@ stage_kernel(LaunchArgs a, int stage)
                         for (int v = 0; v < NV; ++v) sum[v] = xy[v] + (fz_lo[v] - fz[v]);
                         sum[NV] = xy[NV] + (fz[NV] - fz_lo[NV]);
                         rate(sum, q[1], L);
-                        update(icell, L, uo, duo);
+                        update(icell, L, uo, duo, stage == 2 ? add_dist2(dxy2, axis_dist2(d.centre[2], p, n_d)) : 0.0);
                     }
 #pragma unroll
                     for (int v = 0; v <= NV; ++v) fz_lo[v] = fz[v];
@@ -664,7 +732,7 @@ stage_kernel(LaunchArgs a, int stage)
             }
         }
     }
-    if (stage == 2) write_partial<NT>(red, a.part + d.tile0 + item.tile);
+    if constexpr (stage == 2) write_partial<NT>(red, a.part + d.tile0 + item.tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -692,12 +760,16 @@ __global__ void __launch_bounds__((stage_threads<TX, TY>())) reduce_kernel(Launc
     if (ty < TY && gx < n && (ND < 2 || gy < n)) {
         const int z0 = ND == 3 ? tzc * a.zchunk : 0;
         const int z1 = ND == 3 ? min(z0 + a.zchunk, n) : 1;
+        const double n_d = (double)n;
+        double dxy2 = axis_dist2(d.centre[0], gx, n_d);
+        if (ND >= 2) dxy2 = add_dist2(dxy2, axis_dist2(d.centre[1], gy, n_d));
         for (int z = z0; z < z1; ++z) {
             const int64_t idx = (int64_t)z * plane + (ND >= 2 ? (int64_t)gy * n : 0) + gx;
             T q[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) q[v] = u[v * ncell + idx];
-            reduce_cell<T, ND>(a.ph, q, idx, red);
+            reduce_cell<T, ND>(a.ph, d, q, idx, ND == 3 ? add_dist2(dxy2, axis_dist2(d.centre[2], z, n_d)) : dxy2,
+                               red);
         }
     }
     write_partial<NT>(red, a.part + d.tile0 + item.tile);
@@ -719,46 +791,38 @@ __global__ void __launch_bounds__(256) finalize_kernel(const SampleDesc* desc, S
         const TilePartial& tp = part[d.tile0 + t];
         Red o;
         o.s_max = tp.s_max; o.p_max = tp.p_max; o.argmax = tp.argmax; o.n_nf = tp.n_nonfinite; o.n_c2 = tp.n_negc2;
+        o.c_max = tp.c_max; o.p_ball = tp.p_ball; o.a_ball = tp.a2_ball; o.n_p = tp.n_ball_p; o.n_a = tp.n_ball_a;
         r.merge(o);
     }
-    __shared__ double s_s[4], s_p[4];
-    __shared__ int64_t s_a[4];
-    __shared__ int s_n[4], s_c[4];
-    for (int off = 32; off >= 1; off >>= 1) {
-        Red o;
-        o.s_max = __shfl_xor(r.s_max, off, 64);
-        o.p_max = __shfl_xor(r.p_max, off, 64);
-        o.argmax = __shfl_xor(r.argmax, off, 64);
-        o.n_nf = __shfl_xor(r.n_nf, off, 64);
-        o.n_c2 = __shfl_xor(r.n_c2, off, 64);
-        r.merge(o);
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) { s_s[wave] = r.s_max; s_p[wave] = r.p_max; s_a[wave] = r.argmax; s_n[wave] = r.n_nf; s_c[wave] = r.n_c2; }
-    __syncthreads();
+    const Red t = block_merge<256>(r);
     if (threadIdx.x != 0) return;
-    Red t;
-    t.init();
-    for (int w = 0; w < 4; ++w) {
-        Red o;
-        o.s_max = s_s[w]; o.p_max = s_p[w]; o.argmax = s_a[w]; o.n_nf = s_n[w]; o.n_c2 = s_c[w];
-        t.merge(o);
-    }
     if (!initial) {
         st.t = st.last ? d.t_end : st.t + st.dt;
         st.steps += 1;
     }
+    const double ps = t.n_p > 0 ? t.p_ball / (double)t.n_p : 0.0;
+    const double gs = t.n_a > 0 ? t.a_ball / (double)t.n_a : 0.0;
     if (initial) {
         st.p_max = t.p_max;
         st.argmax = t.argmax;
         st.t_at_max = st.t;
+        st.p_sensor = ps;
+        st.t_p_sensor = st.t;
+        st.gas_min = gs;
+        st.t_gas_min = st.t;
+        st.c_max = t.c_max;
     }
     if (t.n_nf > 0) { st.status = OFM_SAMPLE_NONFINITE; st.done = 1; return; }
     if (t.n_c2 > 0) { st.status = OFM_SAMPLE_NEGATIVE_C2; st.done = 1; return; }
-    if (!initial && t.p_max > st.p_max) {
-        st.p_max = t.p_max;
-        st.argmax = t.argmax;
-        st.t_at_max = st.t;
+    if (!initial) {
+        if (t.p_max > st.p_max) {
+            st.p_max = t.p_max;
+            st.argmax = t.argmax;
+            st.t_at_max = st.t;
+        }
+        if (ps > st.p_sensor) { st.p_sensor = ps; st.t_p_sensor = st.t; }
+        if (gs < st.gas_min) { st.gas_min = gs; st.t_gas_min = st.t; }
+        st.c_max = fmax(st.c_max, t.c_max);
     }
     const bool fin = d.n_steps > 0 ? st.steps >= d.n_steps : st.t >= d.t_end;
     if (fin) { st.done = 1; return; }
@@ -926,7 +990,10 @@ __global__ void __launch_bounds__(256) to_conserved_kernel(PhysD ph, const T* u,
 template <typename T, int ND, int TX, int TY>
 static hipError_t launch_stage_t(const LaunchArgs& a, int stage, hipStream_t s)
 {
-    hipLaunchKernelGGL((stage_kernel<T, ND, TX, TY>), dim3(a.n_work), dim3(stage_threads<TX, TY>()), 0, s, a, stage);
+    const dim3 grid(a.n_work), block(stage_threads<TX, TY>());
+    if (stage == 0) hipLaunchKernelGGL((stage_kernel<T, ND, TX, TY, 0>), grid, block, 0, s, a);
+    else if (stage == 1) hipLaunchKernelGGL((stage_kernel<T, ND, TX, TY, 1>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((stage_kernel<T, ND, TX, TY, 2>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 

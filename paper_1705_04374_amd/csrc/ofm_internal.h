@@ -33,6 +33,9 @@ struct SampleDesc {
     double t_end;
     int64_t n_steps;   // > 0: fixed step count
     int64_t max_steps;
+    double centre[3];  // cloud centre (sensors)
+    double r2_p;       // squared radius of the pressure sensor's ball
+    double r2_a;       // squared radius of the gas-fraction sensor's ball
 };
 
 // Dynamic state of one sample, advanced on the device.
@@ -47,6 +50,9 @@ struct SampleState {
     int32_t done;
     int32_t last;      // next step lands on t_end
     int32_t pad;
+    double p_sensor, t_p_sensor;   // running max of the pressure sensor
+    double gas_min, t_gas_min;     // running min of the gas-fraction sensor
+    double c_max;                  // running max of the sound speed
 };
 
 // Per-tile partial of the CFL / QoI reduction.
@@ -56,6 +62,9 @@ struct TilePartial {
     int64_t argmax;
     int32_t n_nonfinite;
     int32_t n_negc2;
+    double c_max;
+    double p_ball, a2_ball;        // sums over the sensors' cells
+    int32_t n_ball_p, n_ball_a;    // and their counts
 };
 
 // One (sample, tile) work item of a batched launch.

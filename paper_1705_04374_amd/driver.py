@@ -160,11 +160,20 @@ def solve_many(ctx: capi.Context, specs: list, bubbles: list, max_batch_bytes: f
     return out, secs
 
 
+# the scalar QoIs of a solve that the estimator can take (ofm_qoi fields)
+QOIS = ("p_max", "p_sensor", "gas_min", "c_max", "peak_distance")
+
+
 class OFMLMC:
     def __init__(self, ctx: capi.Context, solver_cfg: dict, cloud: dict, levels: list, precision: str = "f32",
                  t_end: float = 0.0, n_steps: int = 0, seed: int = 0, net=None,
                  ledger: str | None = None, max_batch_bytes: float = 60e9, max_steps: int = 10 ** 6,
-                 log=print, deadline: float | None = None):
+                 log=print, deadline: float | None = None, qoi: str = "p_max"):
+        if qoi not in QOIS:
+            raise ValueError("qoi must be one of %s" % (QOIS,))
+        if net is not None and qoi != "p_max":
+            raise ValueError("the learned level predicts p_max only")
+        self.qoi = qoi
         self.ctx, self.cfg, self.cloud = ctx, solver_cfg, cloud
         self.precision, self.t_end, self.n_steps, self.seed = precision, t_end, n_steps, seed
         self.net = net          # a surrogate.Surrogate (predict) for the learned level, or None
@@ -231,7 +240,9 @@ class OFMLMC:
                 rows.append(dict(term=k, index=i, qf=qf["p_max"], qc=qc["p_max"] if qc else None, ok=bool(ok),
                                  status_f=qf["status"], status_c=qc["status"] if qc else None,
                                  xf=list(qf.get("x", ())), tf=qf.get("t_at_max"), steps_f=qf.get("steps", 0),
-                                 steps_c=qc.get("steps", 0) if qc else 0, seconds=sf + sc))
+                                 steps_c=qc.get("steps", 0) if qc else 0, seconds=sf + sc,
+                                 Qf={q: qf[q] for q in QOIS if q in qf},
+                                 Qc={q: qc[q] for q in QOIS if q in qc} if qc else None))
             self.ledger.add(rows)
 
         def got(w, q, s):
@@ -261,11 +272,24 @@ class OFMLMC:
                 continue
             for i in range(self.count[k], self.count[k] + m):
                 r = self.ledger.have(k, i)
-                self.q[k]["f"].append(r["qf"])
-                self.q[k]["c"].append(r["qc"] if r["qc"] is not None else 0.0)
+                self.q[k]["f"].append(self.value(r, "f", self.qoi))
+                self.q[k]["c"].append(self.value(r, "c", self.qoi))
                 self.q[k]["ok"].append(1 if r["ok"] else 0)
                 self.time[k] += r["seconds"]
             self.count[k] += m
+
+    @staticmethod
+    def value(row: dict, which: str, qoi: str) -> float:
+        """QoI `qoi` of a ledger row's fine ("f") or coarse ("c") member (0
+        for a term-0 row's coarse member)."""
+        if qoi == "p_max":
+            v = row["q" + which]
+        else:
+            Q = row.get("Q" + which)
+            v = None if Q is None else Q.get(qoi)
+            if Q is not None and v is None:
+                raise KeyError("ledger row %s/%s has no %s" % (row["term"], row["index"], qoi))
+        return 0.0 if v is None else float(v)
 
     def sample(self, k: int, m_new: int):
         """Run m_new fresh samples of term k."""
@@ -288,9 +312,20 @@ class OFMLMC:
         """Measured seconds per sample of each term."""
         return [self.time[k] / max(self.count[k], 1) for k in range(self.L + 1)]
 
-    def evaluate(self, W, classical: bool = False) -> dict:
+    def evaluate(self, W, classical: bool = False, qoi: str | None = None) -> dict:
+        """Estimator on the samples so far: for the driver's QoI, or for
+        another QoI of the same samples (the ledger keeps them all)."""
         import torch
         L = self.L
+        if qoi is not None and qoi != self.qoi:
+            keep = self.q
+            self.q = [dict(f=[self.value(self.ledger.have(k, i), "f", qoi) for i in range(self.count[k])],
+                           c=[self.value(self.ledger.have(k, i), "c", qoi) for i in range(self.count[k])],
+                           ok=keep[k]["ok"]) for k in range(L + 1)]
+            try:
+                return self.evaluate(W, classical)
+            finally:
+                self.q = keep
         mom = self.moments()
         Wd = torch.tensor(W, dtype=torch.float64, device="cuda")
         alpha = torch.ones(L + 1, dtype=torch.float64, device="cuda")
@@ -497,6 +532,13 @@ def _run_workload(a, w, ctx, cloud, T, seed, deadline, log) -> dict:
         out["ofmlmc"] = mc.evaluate(W)
         out["mlmc"] = mc.evaluate(W, classical=True)
         out["cost_seconds"] = sum(mc.time)
+        # the paper's other QoIs on the same samples (the centre pressure
+        # sensor is the QoI of its performance study)
+        try:
+            out["other_qois"] = {q: dict(ofmlmc=mc.evaluate(W, qoi=q), mlmc=mc.evaluate(W, classical=True, qoi=q))
+                                 for q in QOIS if q != "p_max"}
+        except KeyError as e:
+            log("  other QoIs not in the ledger:", e)
         # the same solves one at a time (no batching, a graph per solve), in
         # FP32 and in plain FP64: measured on one cloud per level, times the
         # number of solves at that level

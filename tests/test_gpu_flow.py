@@ -91,6 +91,9 @@ def test_fp64_cloud_100_steps(ctx, cloud, n):
     assert q["status"] == 0 and q["steps"] == 100
     assert math.isclose(q["p_max"], ref["p_max"], rel_tol=1e-10)
     assert q["argmax"] == ref["argmax"]
+    # the paper's other QoIs: sensors, sound speed, peak distance
+    for k in ("p_sensor", "gas_min", "c_max", "peak_distance", "t_p_sensor", "t_gas_min"):
+        assert math.isclose(q[k], ref[k], rel_tol=1e-10, abs_tol=1e-300), (k, q[k], ref[k])
 
 
 def test_fp64_ragged_tiles_and_chunks(ctx):
@@ -202,6 +205,9 @@ def test_fp32_cloud_100_steps(ctx, cloud, n):
     assert np.all(err <= 1e-4), err
     assert abs(q["p_max"] / ref["p_max"] - 1) <= 5e-3
     assert q["status"] == 0
+    for k in ("p_sensor", "c_max"):
+        assert abs(q[k] / ref[k] - 1) <= 5e-3, (k, q[k], ref[k])
+    assert abs(q["gas_min"] - ref["gas_min"]) <= 1e-4 * max(ref["gas_min"], 1e-3)
 
 
 # --------------------------------------------------------------------------
@@ -221,6 +227,8 @@ def test_solve_to_end_time_matches_oracle(ctx):
     assert math.isclose(q["p_max"], ref["p_max"], rel_tol=1e-8)
     assert q["argmax"] == ref["argmax"]
     assert math.isclose(q["t_at_max"], ref["t_at_max"], rel_tol=1e-10)
+    for k in ("p_sensor", "gas_min", "c_max", "peak_distance", "t_p_sensor", "t_gas_min"):
+        assert math.isclose(q[k], ref[k], rel_tol=1e-8, abs_tol=1e-300), (k, q[k], ref[k])
 
 
 def test_batch_equals_single_solves(ctx):

@@ -15,8 +15,9 @@ import pytest
 
 import oracle.flow as F
 from oracle.riemann import ExactRiemann, Side
+from oracle.sampler import sample_cloud
 from workloads.configs import (BASE, EOS, interface_primitives, random_smooth_primitives,
-                               riemann_primitives, solver_config)
+                               cloud_spec, riemann_primitives, solver_config)
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_numbers.json")))
 
@@ -409,6 +410,84 @@ def test_solve_qoi_tracks_running_maximum():
             t += dts[0]
     assert q["p_max"] == best and q["argmax"] == where and q["t_at_max"] == when
     assert q["x"][0] == ((where % n) + 0.5) / n and q["x"][1] == ((where // n) + 0.5) / n
+
+
+def _ball_cells(cfg, r2):
+    n, d = cfg["n"], cfg["ndim"]
+    axes = [(np.arange(n) + 0.5) / n - cfg["center"][a] for a in range(d)]
+    grids = np.meshgrid(*axes[::-1], indexing="ij")          # (z, y, x) order of the state
+    d2 = sum(g * g for g in grids)
+    return (d2 <= r2).ravel()
+
+
+def test_sensor_qois_brute_force():
+    """Sensor QoIs (eq. (sensor)) against a scan over the time levels: the
+    ball averages of p and a2 are the means over the cells whose centres lie
+    in the balls, maxima/minima are tracked over n = 0..steps (earliest time
+    on ties), c_max over cells and levels, the peak distance from x."""
+    n = 32
+    c = solver_config("cloud2d", n)
+    bub = np.array([[0.5, 0.5, 0.0, 0.08], [0.3, 0.62, 0.0, 0.05]])
+    nst = 30
+    q = F.solve(c, bub, n_steps=nst)
+    rp = max(c["cloud_radius"] / 40.0, 1.01 * 0.5 * math.sqrt(2.0) / n)
+    in_p = _ball_cells(c, rp * rp)
+    in_a = _ball_cells(c, c["cloud_radius"] ** 2)
+    U = F.init_state(c, bub)
+    g1, g2 = c["eos"]["gamma1"], c["eos"]["gamma2"]
+    P1 = g1 * c["eos"]["pc1"] / (g1 - 1)
+    ps_best, ps_t, gs_best, gs_t, cmax, t = -np.inf, 0.0, np.inf, 0.0, 0.0, 0.0
+    for st in range(nst + 1):
+        W = F.cons_to_prim(c, U)
+        rho = (W[0] + W[1]).ravel()
+        p, a2 = W[4].ravel(), W[5].ravel()
+        G = (1 - a2) / (g1 - 1) + a2 / (g2 - 1)
+        Pi = (1 - a2) * P1
+        cs = np.sqrt(((G + 1) * p + Pi) / (G * rho))
+        ps, gs = p[in_p].mean(), a2[in_a].mean()
+        if ps > ps_best:
+            ps_best, ps_t = ps, t
+        if gs < gs_best:
+            gs_best, gs_t = gs, t
+        cmax = max(cmax, cs.max())
+        if st < nst:
+            U, dts = F.run_steps(c, U, 1)
+            t += dts[0]
+    assert math.isclose(q["p_sensor"], ps_best, rel_tol=1e-13) and q["t_p_sensor"] == ps_t
+    assert math.isclose(q["gas_min"], gs_best, rel_tol=1e-13) and q["t_gas_min"] == gs_t
+    assert math.isclose(q["c_max"], cmax, rel_tol=1e-13)
+    assert math.isclose(q["peak_distance"], math.hypot(q["x"][0] - 0.5, q["x"][1] - 0.5), rel_tol=1e-15)
+
+
+def test_sensor_closed_forms_at_rest():
+    """At t = 0 the sensor at the centre of the cloud reads the bubble
+    pressure (the ramp starts beyond the cloud), the fastest sound is pure
+    water's at p_inf, a coarse even grid's pressure ball is the 2^d cells
+    around the centre, and the gas sensor counts the lattice points in the
+    cloud's ball."""
+    for cloud, n in (("cloud500", 64), ("cloud2d", 48)):
+        c = solver_config(cloud, n)
+        bub = sample_cloud(cloud_spec(cloud), 170504374, 0, 1)
+        r = F.initial_reduction(c, bub)
+        d = c["ndim"]
+        assert r["n_ball_p"] == 2 ** d                     # R_c/40 is below half a cell diagonal here
+        # cells of the pressure ball are not all water: the sensor reads the
+        # cells' pressure, p_bubble in water and gas alike
+        assert math.isclose(r["p_ball"] / r["n_ball_p"], c["p_bubble"], rel_tol=1e-12)
+        cw = math.sqrt(c["eos"]["gamma1"] * (c["p_inf"] + c["eos"]["pc1"]) / c["rho1"])
+        assert math.isclose(r["c_max"], cw, rel_tol=1e-12)
+        assert r["n_ball_a"] == int(_ball_cells(c, c["cloud_radius"] ** 2).sum())
+    # at 512^3 the pressure ball has radius R_c/40 = 3.84 cells: the oracle's
+    # count on a box around the centre equals the half-integer lattice points
+    # in that ball
+    c = solver_config("cloud500", 512)
+    rp = c["cloud_radius"] / 40.0
+    m = np.arange(-6, 6) + 0.5
+    lattice = int(((m[:, None, None] ** 2 + m[None, :, None] ** 2 + m[None, None, :] ** 2) / 512 ** 2 <= rp * rp).sum())
+    box = ((250, 250, 250), (12, 12, 12))
+    bub = sample_cloud(cloud_spec("cloud500"), 170504374, 0, 1)
+    r = F.reduce(c, F.init_state(c, bub, box), box)
+    assert r["n_ball_p"] == lattice == 208
 
 
 def test_solve_lands_on_end_time_and_caps_steps():
