@@ -349,6 +349,23 @@ int ofm_ofmlmc_optimal_M(ofm_ctx* ctx, int32_t L, const double* sig_t2, const do
                          const int64_t* M_have, int32_t mode, double target, int64_t* M_out,
                          int32_t* flag, void* stream);
 
+/* Inferred variances of level differences (the optional part of step 3 of
+ * the adaptive algorithm, Sec. 2.4.4; App. A.1): a weighted least-squares
+ * line through ln V[q_l - q_{l-1}] (V = Var_f + Var_c - 2 Cov of the term's
+ * moments) against l over the terms l = first..L that have at least two
+ * samples and V > 0, with weights (M_l - 1)/2 (the variance of the logarithm
+ * of a sample variance of Gaussian data is 2/(M - 1)).
+ * mom [dev] (L+1) x 6 as written by ofm_mlmc_moments: the terms
+ * l >= max(first, 1) with fewer than two samples (e.g. a single finest
+ * warm-up sample) are completed in place: both members take the variance of
+ * level l-1 (term l-1's fine variance) and the covariance is set so that
+ * Var_f + Var_c - 2 Cov equals the inferred value.  v_hat [dev] L+1 doubles:
+ * exp of the fitted line for l = first..L, 0 below.  flag [dev] 1 int: 0, or
+ * OFM_ESINGULAR when fewer than two terms qualify (then v_hat is 0 and mom
+ * unchanged).  1 <= L <= 31, 0 <= first <= L.  Asynchronous. */
+int ofm_ofmlmc_fit_indicators(ofm_ctx* ctx, int32_t L, int32_t first, double* mom, double* v_hat,
+                              int32_t* flag, void* stream);
+
 /* ---- learned control variate (not in the paper) ----------------------------
  * A permutation-invariant set network over the bubbles of a cloud, used as an
  * extra low-fidelity level of the OF-MLMC estimator whose optimal coefficient

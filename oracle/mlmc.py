@@ -148,6 +148,49 @@ def optimal_samples(sig_t2, W, M_have, mode: str, target: float):
     return Mhat
 
 
+def fit_indicators(M, Vdiff, first: int = 1):
+    """Inferred variances of level differences (step 3 of the adaptive
+    algorithm, optional part; App. A.1): a least-squares line through
+    y_l = ln V[q_l - q_{l-1}] against l, over the terms l = first..L that have
+    at least 2 samples and V > 0, with Gaussian errors of variance
+    2 / (M_l - 1) (Var[ln s^2] of a sample variance of M Gaussian values),
+    i.e. weights w_l = (M_l - 1) / 2.  Returns (v_hat, ok): v_hat[l] =
+    exp(a + b l) for l = first..L (0 below first); ok is False (v_hat all 0)
+    when fewer than two terms qualify."""
+    L = len(M) - 1
+    pts = [(l, math.log(Vdiff[l]), (M[l] - 1) / 2.0) for l in range(first, L + 1) if M[l] >= 2 and Vdiff[l] > 0]
+    v_hat = np.zeros(L + 1)
+    if len(pts) < 2:
+        return v_hat, False
+    S = sum(w for _, _, w in pts)
+    Sx = sum(w * l for l, _, w in pts)
+    Sy = sum(w * y for _, y, w in pts)
+    Sxx = sum(w * l * l for l, _, w in pts)
+    Sxy = sum(w * l * y for l, y, w in pts)
+    b = (S * Sxy - Sx * Sy) / (S * Sxx - Sx * Sx)
+    a = (Sy - b * Sx) / S
+    for l in range(first, L + 1):
+        v_hat[l] = math.exp(a + b * l)
+    return v_hat, True
+
+
+def infer_missing_terms(mom: list, v_hat, first: int = 1):
+    """Moments of the terms l >= max(first, 1) that have fewer than two
+    samples (the single finest warm-up sample of App. A.1), from the fit:
+    both members take the variance of level l-1 (term l-1's fine members,
+    the closest measured level) and the covariance follows from the inferred
+    difference variance, C = (Vf + Vc - v_hat) / 2 (V[a - b] = Va + Vb - 2C).
+    mom: list of term_moments dicts, updated in place."""
+    for l in range(max(first, 1), len(mom)):
+        if mom[l]["M"] >= 2:
+            continue
+        v = mom[l - 1]["Vf"]
+        mom[l]["Vf"] = v
+        mom[l]["Vc"] = v
+        mom[l]["C"] = (v + v - v_hat[l]) / 2.0
+    return mom
+
+
 def mc_samples(var_L: float, eps: float) -> int:
     """Plain Monte Carlo sample count for error eps at the finest level,
     eq. (speedup) with the square of the ratio (the error of a mean of M

@@ -159,6 +159,57 @@ __global__ void optimal_M_kernel(int L, const double* sig, const double* W, cons
     for (int l = 0; l <= L; ++l) out[l] = fixed[l] ? have[l] : M[l];
 }
 
+// Inferred variances of level differences (the optional part of step 3 of
+// the adaptive algorithm, Sec. 2.4.4; App. A.1): a weighted least-squares
+// line through ln V[q_l - q_{l-1}] against l over the terms l = first..L
+// with at least two samples, weights (M_l - 1)/2 (Gaussian errors of a
+// sample variance's logarithm).  Terms l >= max(first, 1) with fewer than
+// two samples get their moments from the fit: both members take the
+// variance of level l-1, and the covariance the value that gives the
+// inferred difference variance.  One thread: L is a handful of terms.
+__global__ void fit_kernel(int L, int first, double* mom, double* vhat, int32_t* flag)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double S = 0.0, Sx = 0.0, Sy = 0.0, Sxx = 0.0, Sxy = 0.0;
+    int np = 0;
+    for (int l = first; l <= L; ++l) {
+        const double* m = mom + 6 * l;
+        const double V = m[3] + m[4] - 2.0 * m[5];
+        if (m[0] >= 2.0 && V > 0.0) {
+            const double y = log(V), w = (m[0] - 1.0) / 2.0, x = (double)l;
+            S += w;
+            Sx += w * x;
+            Sy += w * y;
+            Sxx += w * x * x;
+            Sxy += w * x * y;
+            ++np;
+        }
+    }
+    for (int l = 0; l <= L; ++l) vhat[l] = 0.0;
+    if (np < 2) {
+        *flag = OFM_ESINGULAR;
+        return;
+    }
+    const double b = (S * Sxy - Sx * Sy) / (S * Sxx - Sx * Sx);
+    const double a = (Sy - b * Sx) / S;
+    for (int l = first; l <= L; ++l) vhat[l] = exp(a + b * (double)l);
+    for (int l = first > 1 ? first : 1; l <= L; ++l) {
+        double* m = mom + 6 * l;
+        if (m[0] >= 2.0) continue;
+        const double v = mom[6 * (l - 1) + 3];
+        m[3] = v;
+        m[4] = v;
+        m[5] = (v + v - vhat[l]) / 2.0;
+    }
+    *flag = 0;
+}
+
+hipError_t launch_fit(int L, int first, double* mom, double* vhat, int32_t* flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(fit_kernel, dim3(1), dim3(64), 0, s, L, first, mom, vhat, flag);
+    return hipGetLastError();
+}
+
 hipError_t launch_moments(const double* qf, const double* qc, const int32_t* ok, int64_t M, double* out,
                           hipStream_t s)
 {

@@ -312,9 +312,17 @@ class OFMLMC:
         """Measured seconds per sample of each term."""
         return [self.time[k] / max(self.count[k], 1) for k in range(self.L + 1)]
 
-    def evaluate(self, W, classical: bool = False, qoi: str | None = None) -> dict:
+    def fit_first(self) -> int:
+        """First term of the indicator fit: the solver differences only (the
+        pair of the coarsest solver level with the network does not follow
+        the geometric decay of the solver's level differences)."""
+        return 2 if self.net is not None else 1
+
+    def evaluate(self, W, classical: bool = False, qoi: str | None = None, fit: bool = False) -> dict:
         """Estimator on the samples so far: for the driver's QoI, or for
-        another QoI of the same samples (the ledger keeps them all)."""
+        another QoI of the same samples (the ledger keeps them all).
+        fit: infer the level-difference variances by the fit of App. A.1
+        and complete the terms with fewer than two samples from it."""
         import torch
         L = self.L
         if qoi is not None and qoi != self.qoi:
@@ -323,10 +331,17 @@ class OFMLMC:
                            c=[self.value(self.ledger.have(k, i), "c", qoi) for i in range(self.count[k])],
                            ok=keep[k]["ok"]) for k in range(L + 1)]
             try:
-                return self.evaluate(W, classical)
+                return self.evaluate(W, classical, fit=fit)
             finally:
                 self.q = keep
         mom = self.moments()
+        v_hat, fit_flag = None, None
+        if fit and L - self.fit_first() >= 1:
+            vh = torch.zeros(L + 1, dtype=torch.float64, device="cuda")
+            ff = torch.zeros(1, dtype=torch.int32, device="cuda")
+            capi.ofm_ofmlmc_fit_indicators(self.ctx, L, self.fit_first(), mom, vh, ff)
+            torch.cuda.synchronize()
+            v_hat, fit_flag = vh.cpu().tolist(), int(ff.item())
         Wd = torch.tensor(W, dtype=torch.float64, device="cuda")
         alpha = torch.ones(L + 1, dtype=torch.float64, device="cuda")
         flag = torch.zeros(1, dtype=torch.int32, device="cuda")
@@ -342,7 +357,7 @@ class OFMLMC:
         return dict(E=E.item(), eps=math.sqrt(max(eps2.item(), 0.0)), alpha=alpha.cpu().tolist(),
                     sigma_t2=sig.cpu().tolist(), singular=int(flag.item()), M=[int(v) for v in m[:, 0]],
                     mean_f=m[:, 1].tolist(), mean_c=m[:, 2].tolist(), var_f=m[:, 3].tolist(),
-                    var_c=m[:, 4].tolist(), cov=m[:, 5].tolist(), W=list(W))
+                    var_c=m[:, 4].tolist(), cov=m[:, 5].tolist(), W=list(W), v_hat=v_hat, fit_flag=fit_flag)
 
     def allocate(self, sig_t2, W, tau: float):
         import torch
@@ -357,16 +372,20 @@ class OFMLMC:
         return out.cpu().tolist(), int(flag.item())
 
     def run(self, rel_tol: float = 0.01, warmup=None, W_model=None, max_iter: int = 10, min_samples: int = 2,
-            max_samples=None, log=None) -> dict:
+            max_samples=None, fit: bool = False, log=None) -> dict:
         """Adaptive loop to eps <= rel_tol |E|.  warmup: explicit counts, or
         eq. (warmup) from W_model (relative cost per term).  max_samples:
-        optional cap per term (None entries = no cap)."""
+        optional cap per term (None entries = no cap).  fit: one warm-up
+        sample on the finest term and its variances inferred from the lower
+        terms (App. A.1) until it has two."""
         log = log or self.log
         L = self.L
         cap = max_samples or [None] * (L + 1)
         if warmup is None:
             W0 = W_model
             warmup = [max(min_samples, int(math.ceil(W0[L] / W0[k] / 2.0 ** (L - k)))) for k in range(L + 1)]
+            if fit and L - self.fit_first() >= 2:
+                warmup[L] = 1
         warmup = [min(w, c) if c else w for w, c in zip(warmup, cap)]
         history = []
         t_start = time.perf_counter()
@@ -374,7 +393,7 @@ class OFMLMC:
         for it in range(max_iter):
             self.sample_terms([max(0, target[k] - self.count[k]) for k in range(L + 1)])
             W = self.work()
-            res = self.evaluate(W)
+            res = self.evaluate(W, fit=fit)
             tau = rel_tol * abs(res["E"])
             res.update(iteration=it, tau=tau, counts=list(self.count), seconds=time.perf_counter() - t_start,
                        sample_seconds=list(self.time))
@@ -486,6 +505,8 @@ def main(argv=None):
     ap.add_argument("--rel-tol", type=float, default=0.01)
     ap.add_argument("--epochs", type=int, default=600)
     ap.add_argument("--max-iter", type=int, default=10)
+    ap.add_argument("--fit", action="store_true",
+                    help="one warm-up sample on the finest level, its variances inferred from the coarser levels")
     ap.add_argument("--time-limit", type=float, default=0.0,
                     help="seconds; batches that would end later are not started (exit status 3, resume later)")
     a = ap.parse_args(argv)
@@ -591,7 +612,7 @@ def _run_workload(a, w, ctx, cloud, T, seed, deadline, log) -> dict:
         single = [1e-6] + [float(n) ** (d + 1) for n in w["levels"]]
         W_model = [single[0], single[1]] + [single[k] + single[k - 1] for k in range(2, len(single))]
         res = mc.run(rel_tol=a.rel_tol, W_model=W_model, max_iter=a.max_iter,
-                     max_samples=[w["M_nn"]] + [None] * len(w["levels"]))
+                     max_samples=[w["M_nn"]] + [None] * len(w["levels"]), fit=a.fit)
         out["ofmlmc"] = res
         out["variance_reduction"] = variance_reduction(res, 1)
     return out

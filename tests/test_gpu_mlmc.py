@@ -90,3 +90,58 @@ def test_singular_system_falls_back_to_ones(ctx):
     capi.ofm_ofmlmc_coefficients(ctx, 2, mom, torch.ones(3, dtype=torch.float64, device="cuda"), alpha, flag)
     assert flag.item() == capi.OFM_ESINGULAR
     assert alpha.cpu().tolist() == [1.0, 1.0, 1.0]
+
+
+@pytest.mark.parametrize("Ms,first", [([65536, 2000, 300, 40, 1], 1), ([4000, 900, 120, 9, 1, 1], 0),
+                                      ([5000, 700, 60, 12], 1)])
+def test_indicator_fit_matches_oracle(ctx, Ms, first):
+    """Inferred level-difference variances (App. A.1) and the completed
+    moments of the terms with fewer than two samples: <= 1e-12 relative."""
+    import torch
+    from paper_1705_04374_amd import capi
+    L = len(Ms) - 1
+    terms = toy_terms(L, Ms, 7 + L)
+    mom = torch.zeros((L + 1, 6), dtype=torch.float64, device="cuda")
+    refs = []
+    for l, (qf, qc, ok) in enumerate(terms):
+        ok = np.ones_like(ok)
+        capi.ofm_mlmc_moments(ctx, torch.tensor(qf, device="cuda"),
+                              torch.tensor(qc, device="cuda") if qc is not None else None,
+                              torch.tensor(ok, device="cuda"), mom[l])
+        refs.append(O.term_moments(qf, qc, ok.astype(bool)))
+    v_ref, ok_ref = O.fit_indicators([r["M"] for r in refs],
+                                     [r["Vf"] + r["Vc"] - 2 * r["C"] for r in refs], first)
+    assert ok_ref
+    O.infer_missing_terms(refs, v_ref, first)
+    v_hat = torch.full((L + 1,), -1.0, dtype=torch.float64, device="cuda")
+    flag = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    capi.ofm_ofmlmc_fit_indicators(ctx, L, first, mom, v_hat, flag)
+    assert flag.item() == 0
+    np.testing.assert_allclose(v_hat.cpu().numpy(), v_ref, rtol=1e-12, atol=0)
+    m = mom.cpu().numpy()
+    for l, r in enumerate(refs):
+        for j, k in ((3, "Vf"), (4, "Vc"), (5, "C")):
+            assert abs(m[l, j] - r[k]) <= 1e-12 * max(abs(r[k]), 1e-300), (l, k)
+    # the completed finest terms give the inferred difference variance
+    for l in range(max(first, 1), L + 1):
+        if Ms[l] < 2:
+            assert abs(m[l, 3] + m[l, 4] - 2 * m[l, 5] - v_ref[l]) <= 1e-12 * v_ref[l] * 10
+
+
+def test_indicator_fit_needs_two_terms(ctx):
+    import torch
+    from paper_1705_04374_amd import capi
+    mom = torch.zeros((3, 6), dtype=torch.float64, device="cuda")
+    mom[:, 0] = torch.tensor([100.0, 50.0, 1.0], dtype=torch.float64)
+    mom[:, 3] = 2.0
+    mom[1, 4] = 1.5
+    mom[1, 5] = 1.0
+    before = mom.clone()
+    v_hat = torch.full((3,), -1.0, dtype=torch.float64, device="cuda")
+    flag = torch.zeros(1, dtype=torch.int32, device="cuda")
+    capi.ofm_ofmlmc_fit_indicators(ctx, 2, 1, mom, v_hat, flag)
+    assert flag.item() == capi.OFM_ESINGULAR
+    assert v_hat.cpu().tolist() == [0.0, 0.0, 0.0]
+    assert torch.equal(mom, before)
+    _, ok = O.fit_indicators([100, 50, 1], [2.0, 1.5, 0.0], 1)
+    assert not ok

@@ -220,3 +220,58 @@ def test_optimal_samples_keeps_computed_levels():
 
 def test_mc_sample_count():
     assert O.mc_samples(4.0, 0.1) == 400
+
+
+# --------------------------------------------------------------------------
+# indicator fit (App. A.1)
+# --------------------------------------------------------------------------
+
+def test_fit_recovers_an_exact_exponential_decay():
+    """Data exactly on V_l = c r^l: the fitted line goes through every point
+    whatever the weights, and extrapolates to the unmeasured finest term."""
+    c, r = 3.7e15, 0.31
+    M = [0, 40, 9, 3, 1]
+    V = [0.0] + [c * r ** l for l in range(1, 5)]
+    V[4] = 0.0                                   # a single sample: no variance
+    v_hat, ok = O.fit_indicators(M, V, first=1)
+    assert ok
+    for l in range(1, 5):
+        assert math.isclose(v_hat[l], c * r ** l, rel_tol=1e-12)
+
+
+def test_fit_two_points_is_the_line_through_them_and_minimises_weighted_residual():
+    M = [0, 11, 5, 1]
+    V = [0.0, 2.0e15, 5.0e14, 0.0]
+    v_hat, ok = O.fit_indicators(M, V)
+    assert ok and math.isclose(v_hat[1], 2.0e15, rel_tol=1e-13) and math.isclose(v_hat[2], 5.0e14, rel_tol=1e-13)
+    assert math.isclose(v_hat[3], 1.25e14, rel_tol=1e-12)      # halving in the log per level
+    # three noisy points: the fitted (a, b) zero the gradient of the weighted
+    # squared residual sum_l w_l (ln V_l - a - b l)^2
+    M = [0, 30, 12, 6]
+    V = [0.0, 2.0e15, 7.0e14, 1.0e14]
+    v_hat, ok = O.fit_indicators(M, V)
+    b = math.log(v_hat[2] / v_hat[1])
+    a = math.log(v_hat[1]) - b
+    g_a = g_b = 0.0
+    for l in (1, 2, 3):
+        w = (M[l] - 1) / 2.0
+        res = math.log(V[l]) - a - b * l
+        g_a += w * res
+        g_b += w * res * l
+    assert abs(g_a) < 1e-9 and abs(g_b) < 1e-9
+    # too few points
+    _, ok = O.fit_indicators([0, 5, 1], [0.0, 1e14, 0.0])
+    assert not ok
+
+
+def test_inferred_finest_term_moments():
+    """A single finest sample: both members take the next level's variance and
+    the covariance gives back the inferred difference variance."""
+    mom = [dict(M=100, Vf=4.0e15, Vc=0.0, C=0.0), dict(M=20, Vf=5.0e15, Vc=4.1e15, C=4.3e15),
+           dict(M=1, Vf=0.0, Vc=0.0, C=0.0)]
+    v_hat = np.array([0.0, 5.0e14, 1.2e14])
+    O.infer_missing_terms(mom, v_hat, first=1)
+    m = mom[2]
+    assert m["Vf"] == m["Vc"] == 5.0e15
+    assert math.isclose(m["Vf"] + m["Vc"] - 2 * m["C"], 1.2e14, rel_tol=1e-12)
+    assert mom[1]["C"] == 4.3e15                       # measured terms untouched
