@@ -21,7 +21,9 @@ The JSON line also carries
   cpu_baseline the serial FP64 oracle timed on this host's cores on a bounded
                sample of the same workload (one 64^3 box of the 256^3 cloud per
                process, 4 steps each);
-  fp64         the same measurement with the stencil in double.
+  fp64         the same measurement with the stencil in double;
+  weno3        the same measurement (float stencil, the tile tuned above) with
+               the third-order reconstruction the paper also allows.
 """
 from __future__ import annotations
 
@@ -82,6 +84,7 @@ def parse():
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 side measurement")
+    ap.add_argument("--no-weno3", action="store_true", help="skip the WENO3 side measurement")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true", help="use the default tile instead of autotuning")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -246,6 +249,13 @@ def main():
                        "tile": None if r64["tuned"] is None else {k: r64["tuned"][k] for k in ("tx", "ty", "zchunk")},
                        "hbm_frac": round(c64 * WORDS_PER_CELL_STEP * 8 / 3.0 / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                        "alu_frac": round(c64 * FLOPS_PER_CELL_STAGE / (ms64 * 1e-3) / 1e12 / VALU_PEAK_TFLOPS["f64"], 4)}
+    if not a.no_weno3 and a.precision == "f32":
+        k3 = max(4, a.steps // 3)
+        r3 = measure(ctx, capi, dict(cfg, weno_order=3), bub, "f32", k3, 1, tune=False)
+        kt3 = r3["kt"]
+        out["weno3"] = {"value": cells * k3 / r3["wall"], "unit": "cell-updates/s", "steps": k3,
+                        "avg_stage_launch_ms": round(kt3["total_ms"] / max(kt3["launches"], 1), 4),
+                        "status": r3["q"]["status"]}
     if not a.no_cpu:
         try:
             out["cpu_baseline"] = cpu_baseline(cfg, bub)

@@ -57,6 +57,15 @@ extern "C" {
 #define OFM_F64 1   /* everything in double */
 #define OFM_BC_ZERO_GRADIENT 0
 #define OFM_BC_PERIODIC      1
+/* Characteristic far field (Sec. 3.1, after Poinsot and Lele): ghost cells
+ * outside a domain side take the nearest cell's primitives with the normal
+ * velocity and pressure set so that the outgoing acoustic invariant
+ * p + s Z u_n (Z = rho c, s = +1 on the high side, -1 on the low side) is
+ * kept and the incoming one moves a fraction beta = sigma h (sigma = 0.25,
+ * unit domain) towards its far-field value p_inf of the fluid at rest: the
+ * boundary relaxes towards p_inf at the rate sigma c, and outgoing waves
+ * leave. */
+#define OFM_BC_CHARACTERISTIC 2
 #define OFM_MODE_TOLERANCE 0
 #define OFM_MODE_BUDGET    1
 
@@ -82,20 +91,21 @@ typedef struct {
     int32_t ndim;        /* 1, 2 or 3 */
     int32_t n;           /* cells per side, 8 <= n <= 4096 */
     int32_t precision;   /* OFM_F32 or OFM_F64 */
-    int32_t bc;          /* OFM_BC_* */
+    int32_t bc;          /* OFM_BC_*; the far field takes p_inf below */
     int32_t n_sub;       /* sub-samples per axis for the initial a2 (n_sub^ndim <= 64) */
-    int32_t reserved;
+    int32_t weno_order;  /* reconstruction (Sec. 2.2 allows third or fifth order):
+                            0 or 5 = WENO5, 3 = WENO3 (Jiang-Shu); else OFM_EINVAL */
     double cfl;          /* Courant number (0.3 in the paper, Sec. 3.1) */
     ofm_eos eos;
     double rho1, rho2;   /* initial phase densities (also the scale below which a
                             negative partial density counts as round-off) */
     double p_bubble;     /* pressure inside the cloud */
-    double p_inf;        /* ambient pressure */
+    double p_inf;        /* ambient pressure (and far-field pressure of OFM_BC_CHARACTERISTIC) */
     double center[3];    /* cloud centre */
     double cloud_radius; /* the ramp to p_inf starts at cloud_radius + ramp_delta */
     double ramp_delta;
     double ramp_width;
-    double weno_eps;     /* WENO5 smoothness epsilon (absolute) */
+    double weno_eps;     /* WENO smoothness epsilon (absolute) */
     double t_end;        /* end time when n_steps == 0 */
     int64_t n_steps;     /* > 0: run exactly this many steps, t_end ignored */
     int64_t max_steps;   /* step cap (status OFM_SAMPLE_MAX_STEPS) */
@@ -151,7 +161,8 @@ typedef struct {
 } ofm_state_view;
 
 /* One member of a batched solve.  Items of one call share ndim, precision,
- * bc, eos, rho1, rho2 and weno_eps; n, t_end and the cloud may differ.  A coupled
+ * bc, eos, rho1, rho2, weno_eps and weno_order (and p_inf under
+ * OFM_BC_CHARACTERISTIC); n, t_end and the cloud may differ.  A coupled
  * fine/coarse pair is two items with the same bubbles (Sec. 2.4.1). */
 typedef struct {
     const ofm_solve_spec* spec;

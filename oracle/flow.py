@@ -40,7 +40,7 @@ class Spec(C.Structure):
         ("p_bubble", C.c_double), ("p_inf", C.c_double),
         ("center", C.c_double * 3),
         ("cloud_radius", C.c_double), ("ramp_delta", C.c_double), ("ramp_width", C.c_double),
-        ("weno_eps", C.c_double),
+        ("weno_eps", C.c_double), ("weno_order", C.c_int32), ("pad", C.c_int32),
     ]
 
 
@@ -81,7 +81,12 @@ def lib():
         L.orc_prim_to_cons.argtypes = [C.POINTER(Spec), _dp, _dp]
         L.orc_weno5_right_edge.restype = C.c_double
         L.orc_weno5_right_edge.argtypes = [C.c_double] * 6
+        L.orc_weno3_right_edge.restype = C.c_double
+        L.orc_weno3_right_edge.argtypes = [C.c_double] * 4
         L.orc_hllc.argtypes = [C.POINTER(Spec), C.c_int, _dp, _dp, _dp]
+        L.orc_cell_edges.restype = C.c_int
+        L.orc_char_ghost.argtypes = [C.POINTER(Spec), C.c_int, C.c_int, C.c_double, _dp, _dp]
+        L.orc_cell_edges.argtypes = [C.POINTER(Spec)] + [_dp] * 5 + [C.c_double, _dp, _dp]
         L.orc_rhs.argtypes = [C.POINTER(Spec), C.POINTER(Box), _dp, _dp, C.POINTER(C.c_int64)]
         L.orc_rk_coefficients.argtypes = [_dp, _dp]
         L.orc_step.argtypes = [C.POINTER(Spec), C.POINTER(Box), _dp, C.c_double]
@@ -103,7 +108,7 @@ def make_spec(cfg: dict) -> Spec:
     s = Spec()
     s.ndim = cfg["ndim"]
     s.n = cfg["n"]
-    s.bc = {"zero_gradient": 0, "periodic": 1}[cfg.get("bc", "zero_gradient")]
+    s.bc = {"zero_gradient": 0, "periodic": 1, "characteristic": 2}[cfg.get("bc", "zero_gradient")]
     s.n_sub = cfg.get("n_sub", 4)
     s.cfl = cfg.get("cfl", 0.3)
     eos = cfg["eos"]
@@ -118,6 +123,7 @@ def make_spec(cfg: dict) -> Spec:
     s.ramp_delta = cfg.get("ramp_delta", R / 20.0)
     s.ramp_width = cfg.get("ramp_width", R / 3.0)
     s.weno_eps = cfg.get("weno_eps", 1e-6)
+    s.weno_order = cfg.get("weno_order", 5)
     return s
 
 
@@ -264,6 +270,34 @@ def solve(cfg: dict, bubbles: np.ndarray, t_end: float = 0.0, n_steps: int = 0,
 
 def weno5_right_edge(a, b, c, d, e, eps=1e-6) -> float:
     return lib().orc_weno5_right_edge(a, b, c, d, e, eps)
+
+
+def weno3_right_edge(b, c, d, eps=1e-6) -> float:
+    return lib().orc_weno3_right_edge(b, c, d, eps)
+
+
+def cell_edges(cfg: dict, stencil):
+    """Left and right edge primitives of the centre cell of a five-cell
+    primitive stencil [5][nv] along one axis, with the positivity checks;
+    returns (left, right, replaced)."""
+    s = make_spec(cfg)
+    nv = nvars(cfg["ndim"])
+    st = [np.ascontiguousarray(stencil[k], dtype=np.float64) for k in range(5)]
+    assert all(x.size == nv for x in st)
+    lo, hi = np.zeros(nv), np.zeros(nv)
+    r = lib().orc_cell_edges(C.byref(s), *[_ptr(x) for x in st], s.weno_eps, _ptr(lo), _ptr(hi))
+    return lo, hi, bool(r)
+
+
+def char_ghost(cfg: dict, axis: int, side: int, beta: float, w) -> np.ndarray:
+    """Ghost primitives of the characteristic far-field condition outside
+    the domain side (axis, side = -1 low / +1 high) next to a cell with
+    primitives w."""
+    s = make_spec(cfg)
+    x = np.ascontiguousarray(w, dtype=np.float64)
+    g = np.zeros_like(x)
+    lib().orc_char_ghost(C.byref(s), axis, side, beta, _ptr(x), _ptr(g))
+    return g
 
 
 def hllc(cfg: dict, direction: int, wl, wr) -> np.ndarray:

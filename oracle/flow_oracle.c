@@ -29,11 +29,14 @@
  *                Pi(a2)    = (1-a2) g1 pc1/(g1-1) + a2 g2 pc2/(g2-1),
  *                p = (E - rho|u|^2/2 - Pi)/Gamma;
  *   sound speed  frozen mixture value c^2 = ((Gamma+1) p + Pi)/(Gamma rho);
- *   WENO         fifth-order Jiang-Shu, eps = spec->weno_eps (absolute);
+ *   WENO         fifth-order Jiang-Shu (weno_order 5, the default) or
+ *                third-order Jiang-Shu (weno_order 3; the paper allows
+ *                either), eps = spec->weno_eps (absolute);
  *   positivity   each cell is reconstructed along each axis on its own
  *                (both edge values); a partial density that would be negative
  *                at an edge or at the interior Gauss-Lobatto point that keeps
- *                the cell mean (Zhang-Shu), or an a2 that would leave [0, 1]
+ *                the cell mean (Zhang-Shu; four-point rule for WENO5, three-
+ *                point (Simpson) rule for WENO3), or an a2 that would leave [0, 1]
  *                there, takes the cell value at both edges (first order for
  *                that variable); if an edge state then has (Gamma+1) p + Pi
  *                <= 0 the whole cell is first order;
@@ -44,7 +47,18 @@
  *                B = (1/4, 8/9, 3/4);
  *   CFL          dt = cfl h / max_cells max_d (|u_d| + c), taken at the start
  *                of the step, kept for its three stages, clipped to land on T;
- *   boundary     zero-gradient (ghost = nearest cell of the box) or periodic;
+ *   boundary     zero-gradient (ghost = nearest cell of the box), periodic, or
+ *                characteristic far field (Sec. 3.1, after Poinsot and Lele):
+ *                ghost cells outside a domain side take the primitives of the
+ *                nearest cell with the normal velocity and pressure changed
+ *                so that the outgoing acoustic invariant p + s Z u_n
+ *                (Z = rho c, s = +1 on the high side, -1 on the low side) is
+ *                kept and the incoming one p - s Z u_n is moved a fraction
+ *                beta = sigma h / L (sigma = 0.25, L = 1) towards its
+ *                far-field value p_inf (fluid at rest); the upwind update of
+ *                the boundary cell then relaxes its incoming invariant
+ *                towards p_inf at the rate K = beta c / h = sigma c / L, the
+ *                penalty rate of Poinsot and Lele at low Mach number;
  *   init         a2 = fraction of n_s^d midpoint sub-samples inside the union
  *                of bubbles; smoothstep pressure ramp from p_bubble to p_inf
  *                starting ramp_delta outside the cloud radius, width
@@ -64,7 +78,8 @@
 typedef struct {
     int32_t ndim;      /* 1, 2 or 3 */
     int32_t n;         /* cells per side of the full unit domain */
-    int32_t bc;        /* 0 = zero-gradient, 1 = periodic (box must be the domain) */
+    int32_t bc;        /* 0 = zero-gradient, 1 = periodic (box must be the domain),
+                          2 = characteristic far field */
     int32_t n_sub;     /* sub-samples per axis for the initial volume fraction */
     double cfl;
     double gamma1, pc1, gamma2, pc2;   /* phase 1 = water, phase 2 = air */
@@ -73,6 +88,8 @@ typedef struct {
     double center[3];
     double cloud_radius, ramp_delta, ramp_width;
     double weno_eps;
+    int32_t weno_order; /* 5 (or 0) = WENO5, 3 = WENO3 */
+    int32_t pad;
 } orc_spec;
 
 /* A box of cells [lo, lo+len) of the global grid, per axis. */
@@ -218,6 +235,22 @@ double orc_weno5_right_edge(double a, double b, double c, double d, double e, do
     return (w0 * p0 + w1 * p1 + w2 * p2) / (w0 + w1 + w2);
 }
 
+/* WENO3 (Jiang-Shu, two candidate stencils of two cells) value at the right
+ * edge of cell c from the cell averages b, c, d (cells c-1 .. c+1): candidates
+ * (3c - b)/2 and (c + d)/2 with ideal weights 1/3 and 2/3 and indicators
+ * (c - b)^2 and (d - c)^2.  The left-edge value is the formula applied to the
+ * mirrored stencil. */
+double orc_weno3_right_edge(double b, double c, double d, double eps)
+{
+    double p0 = (3.0 * c - b) / 2.0;
+    double p1 = (c + d) / 2.0;
+    double b0 = (c - b) * (c - b);
+    double b1 = (d - c) * (d - c);
+    double w0 = (1.0 / 3.0) / ((eps + b0) * (eps + b0));
+    double w1 = (2.0 / 3.0) / ((eps + b1) * (eps + b1));
+    return (w0 * p0 + w1 * p1) / (w0 + w1);
+}
+
 /* ------------------------------------------------------------------ */
 /* HLLC flux with the volume-fraction adaptation (Sec. 2.2)            */
 /* ------------------------------------------------------------------ */
@@ -299,12 +332,14 @@ void orc_hllc(const orc_spec* s, int dir, const double* wl, const double* wr, do
 #define ORC_ROUND_TOL 1e-12
 
 /* Edge values of the centre cell c of the primitive stencil a, b, c, d, e
- * (cells c-2 .. c+2 along one axis): left edge into wminus, right edge into
- * wplus (either may be NULL).
+ * (cells c-2 .. c+2 along one axis; WENO3 reads b, c, d only): left edge into
+ * wminus, right edge into wplus (either may be NULL).
  *   - each partial density keeps its reconstruction only if it is >= 0 at
- *     both edges and at the interior value (12 mean - left - right)/10 of the
- *     four-point Gauss-Lobatto rule that reproduces the cell mean (Zhang-Shu
- *     positivity condition), up to round-off: ORC_ROUND_TOL times the
+ *     both edges and at the interior value that, with the two edges,
+ *     reproduces the cell mean under the Gauss-Lobatto rule exact for the
+ *     reconstruction's degree (Zhang-Shu positivity condition): the four-point
+ *     rule for WENO5, (12 mean - left - right)/10, the three-point rule for
+ *     WENO3, (6 mean - left - right)/4; up to round-off: ORC_ROUND_TOL times the
  *     phase's reference density (the initial rho_k) or the largest magnitude
  *     of that partial density in the stencil, whichever is larger; otherwise
  *     both its edges take the cell value;
@@ -321,9 +356,15 @@ int orc_cell_edges(const orc_spec* s, const double* a, const double* b, const do
     int nd = s->ndim;
     int nv = nvars(nd);
     double lm[8], lp[8];
+    int third = s->weno_order == 3;
     for (int v = 0; v < nv; ++v) {
-        lp[v] = orc_weno5_right_edge(a[v], b[v], c[v], d[v], e[v], eps);
-        lm[v] = orc_weno5_right_edge(e[v], d[v], c[v], b[v], a[v], eps);
+        if (third) {
+            lp[v] = orc_weno3_right_edge(b[v], c[v], d[v], eps);
+            lm[v] = orc_weno3_right_edge(d[v], c[v], b[v], eps);
+        } else {
+            lp[v] = orc_weno5_right_edge(a[v], b[v], c[v], d[v], e[v], eps);
+            lm[v] = orc_weno5_right_edge(e[v], d[v], c[v], b[v], a[v], eps);
+        }
     }
     int keep[8];
     for (int v = 0; v < nv; ++v) keep[v] = 1;
@@ -334,14 +375,14 @@ int orc_cell_edges(const orc_spec* s, const double* a, const double* b, const do
         double big = v == 0 ? s->rho1 : s->rho2;
         big = fmax(big, fmax(fmax(fabs(a[v]), fabs(b[v])), fmax(fmax(fabs(c[v]), fabs(d[v])), fabs(e[v]))));
         double tol = -ORC_ROUND_TOL * big;
-        double mid = (12.0 * c[v] - lm[v] - lp[v]) / 10.0;
+        double mid = third ? (6.0 * c[v] - lm[v] - lp[v]) / 4.0 : (12.0 * c[v] - lm[v] - lp[v]) / 10.0;
         if (!(lm[v] >= tol) || !(lp[v] >= tol) || !(mid >= tol)) keep[v] = 0;
     }
     /* the volume fraction */
     {
         int v = 3 + nd;
         double lo = -ORC_ROUND_TOL, hi = 1.0 + ORC_ROUND_TOL;
-        double mid = (12.0 * c[v] - lm[v] - lp[v]) / 10.0;
+        double mid = third ? (6.0 * c[v] - lm[v] - lp[v]) / 4.0 : (12.0 * c[v] - lm[v] - lp[v]) / 10.0;
         if (!(lm[v] >= lo && lm[v] <= hi) || !(lp[v] >= lo && lp[v] <= hi) || !(mid >= lo && mid <= hi)) keep[v] = 0;
     }
     for (int v = 0; v < nv; ++v)
@@ -403,6 +444,44 @@ static int ghost_map(const grid* g, int axis, int i)
 }
 
 /* ------------------------------------------------------------------ */
+/* Characteristic far-field ghost state (Sec. 3.1)                     */
+/* ------------------------------------------------------------------ */
+
+#define ORC_NR_SIGMA 0.25
+
+/* Ghost primitives g outside the domain side (axis, side = -1 low / +1 high)
+ * from the primitives w of the nearest cell: the outgoing acoustic invariant
+ * p + side Z u_n is kept and the incoming one Rm = p - side Z u_n moves to
+ * Rm + beta (p_inf - Rm); solving the two for p and u_n gives
+ * p_g = p + delta and u_n,g = u_n - side delta / Z with delta =
+ * beta (p_inf - Rm) / 2.  Everything else is copied (zero gradient); so is
+ * the whole state if (rho c)^2 is not positive. */
+void orc_char_ghost(const orc_spec* s, int axis, int side, double beta, const double* w, double* g)
+{
+    int nd = s->ndim;
+    int nv = nvars(nd);
+    for (int v = 0; v < nv; ++v) g[v] = w[v];
+    double rho = w[0] + w[1];
+    double a2 = w[3 + nd];
+    double p = w[2 + nd];
+    double un = w[2 + axis];
+    double G = mix_gamma(s, a2);
+    double z2 = rho * ((G + 1.0) * p + mix_pi(s, a2)) / G;     /* (rho c)^2 */
+    if (!(z2 > 0.0)) return;
+    double Z = sqrt(z2);
+    double Rm = p - side * Z * un;
+    double delta = 0.5 * beta * (s->p_inf - Rm);
+    g[2 + nd] = p + delta;
+    g[2 + axis] = un - side * delta / Z;
+}
+
+/* beta of the characteristic boundary for this grid */
+static double char_beta(const orc_spec* s)
+{
+    return ORC_NR_SIGMA / (double)s->n;
+}
+
+/* ------------------------------------------------------------------ */
 /* Right-hand side L(U) (eq. (ode))                                    */
 /* ------------------------------------------------------------------ */
 
@@ -443,6 +522,13 @@ void orc_rhs(const orc_spec* s, const orc_box* box, const double* U, double* Lou
                 cc[dir] = ghost_map(&g, dir, pos[dir] - 4 + o);
                 int64_t ci = cell_index(&g, cc[0], cc[1], cc[2]);
                 for (int v = 0; v < nv; ++v) st[o][v] = W[v * nc + ci];
+                /* a ghost outside a domain side under the far-field condition */
+                int gi = g.box.lo[dir] + pos[dir] - 4 + o;
+                if (s->bc == 2 && (gi < 0 || gi >= s->n)) {
+                    double tmp[8];
+                    orc_char_ghost(s, dir, gi < 0 ? -1 : 1, char_beta(s), st[o], tmp);
+                    for (int v = 0; v < nv; ++v) st[o][v] = tmp[v];
+                }
             }
             /* left state: right edge of cell i-1 (stencil slot 3);
              * right state: left edge of cell i (stencil slot 4) */

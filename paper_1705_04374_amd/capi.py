@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libofm.so")
 
 OFM_OK, OFM_EINVAL, OFM_ENOMEM, OFM_EHIP, OFM_EUNSUPPORTED, OFM_ESINGULAR, OFM_EINFEASIBLE = 0, -1, -2, -3, -4, -5, -6
 OFM_F32, OFM_F64 = 0, 1
-OFM_BC_ZERO_GRADIENT, OFM_BC_PERIODIC = 0, 1
+OFM_BC_ZERO_GRADIENT, OFM_BC_PERIODIC, OFM_BC_CHARACTERISTIC = 0, 1, 2
 OFM_MODE_TOLERANCE, OFM_MODE_BUDGET = 0, 1
 SAMPLE_OK, SAMPLE_NONFINITE, SAMPLE_NEGATIVE_C2, SAMPLE_MAX_STEPS = 0, 1, 2, 3
 
@@ -48,7 +48,7 @@ class Eos(C.Structure):
 class SolveSpec(C.Structure):
     _fields_ = [
         ("ndim", C.c_int32), ("n", C.c_int32), ("precision", C.c_int32), ("bc", C.c_int32),
-        ("n_sub", C.c_int32), ("reserved", C.c_int32),
+        ("n_sub", C.c_int32), ("weno_order", C.c_int32),
         ("cfl", C.c_double), ("eos", Eos),
         ("rho1", C.c_double), ("rho2", C.c_double), ("p_bubble", C.c_double), ("p_inf", C.c_double),
         ("center", C.c_double * 3), ("cloud_radius", C.c_double), ("ramp_delta", C.c_double),
@@ -210,7 +210,8 @@ def make_spec(cfg: dict, precision: str = "f64", t_end: float = 0.0, n_steps: in
     s.ndim = cfg["ndim"]
     s.n = cfg["n"]
     s.precision = {"f32": OFM_F32, "f64": OFM_F64}[precision]
-    s.bc = {"zero_gradient": OFM_BC_ZERO_GRADIENT, "periodic": OFM_BC_PERIODIC}[cfg.get("bc", "zero_gradient")]
+    s.bc = {"zero_gradient": OFM_BC_ZERO_GRADIENT, "periodic": OFM_BC_PERIODIC,
+            "characteristic": OFM_BC_CHARACTERISTIC}[cfg.get("bc", "zero_gradient")]
     s.n_sub = cfg.get("n_sub", 4)
     s.cfl = cfg.get("cfl", 0.3)
     e = cfg["eos"]
@@ -225,6 +226,7 @@ def make_spec(cfg: dict, precision: str = "f64", t_end: float = 0.0, n_steps: in
     s.ramp_delta = cfg.get("ramp_delta", R / 20.0)
     s.ramp_width = cfg.get("ramp_width", R / 3.0)
     s.weno_eps = cfg.get("weno_eps", 1e-6)
+    s.weno_order = cfg.get("weno_order", 5)
     s.t_end = t_end
     s.n_steps = n_steps
     s.max_steps = max_steps

@@ -84,6 +84,9 @@ static PhysD make_phys(const ofm_solve_spec& s)
     p.eps = s.weno_eps;
     p.rho1 = s.rho1;
     p.rho2 = s.rho2;
+    p.p_far = s.p_inf;
+    p.order = s.weno_order == 3 ? 3 : 5;
+    p.pad = 0;
     return p;
 }
 
@@ -93,13 +96,16 @@ static int validate(ofm_ctx* ctx, const ofm_solve_spec* s)
     if (s->ndim < 1 || s->ndim > 3) return fail(ctx, OFM_EINVAL, "ndim must be 1, 2 or 3 (got %d)", s->ndim);
     if (s->n < 8 || s->n > 4096) return fail(ctx, OFM_EINVAL, "n must be in [8, 4096] (got %d)", s->n);
     if (s->precision != OFM_F32 && s->precision != OFM_F64) return fail(ctx, OFM_EINVAL, "bad precision");
-    if (s->bc != OFM_BC_ZERO_GRADIENT && s->bc != OFM_BC_PERIODIC) return fail(ctx, OFM_EINVAL, "bad bc");
+    if (s->bc != OFM_BC_ZERO_GRADIENT && s->bc != OFM_BC_PERIODIC && s->bc != OFM_BC_CHARACTERISTIC)
+        return fail(ctx, OFM_EINVAL, "bad bc");
     int nsub = 1;
     for (int a = 0; a < s->ndim; ++a) nsub *= s->n_sub;
     if (s->n_sub < 1 || nsub > 64) return fail(ctx, OFM_EINVAL, "n_sub^ndim must be in [1, 64]");
     if (!(s->cfl > 0.0 && s->cfl <= 1.0)) return fail(ctx, OFM_EINVAL, "cfl must be in (0, 1]");
     if (!(s->eos.gamma1 > 1.0) || !(s->eos.gamma2 > 1.0)) return fail(ctx, OFM_EINVAL, "gamma must exceed 1");
     if (!(s->weno_eps > 0.0)) return fail(ctx, OFM_EINVAL, "weno_eps must be positive");
+    if (s->weno_order != 0 && s->weno_order != 3 && s->weno_order != 5)
+        return fail(ctx, OFM_EINVAL, "weno_order must be 0, 3 or 5 (got %d)", s->weno_order);
     if (!(s->rho1 > 0.0) || !(s->rho2 > 0.0)) return fail(ctx, OFM_EINVAL, "densities must be positive");
     if (!(s->ramp_width > 0.0)) return fail(ctx, OFM_EINVAL, "ramp_width must be positive");
     if (s->max_steps < 1) return fail(ctx, OFM_EINVAL, "max_steps must be >= 1");
@@ -257,9 +263,13 @@ static int run_begin(ofm_ctx* ctx, ofm_run& r, bool init, int64_t dts_len, hipSt
     const int prec = s0.precision, nd = s0.ndim, bc = s0.bc;
     for (const Member& m : mem) {
         if (m.spec.ndim != nd || m.spec.precision != prec || m.spec.bc != bc || m.spec.weno_eps != s0.weno_eps ||
-            m.spec.rho1 != s0.rho1 || m.spec.rho2 != s0.rho2 || memcmp(&m.spec.eos, &s0.eos, sizeof(ofm_eos)) != 0)
-            return fail(ctx, OFM_EINVAL, "batched items must share ndim, precision, bc, eos, rho1, rho2 and weno_eps");
+            (m.spec.weno_order == 3) != (s0.weno_order == 3) || m.spec.rho1 != s0.rho1 || m.spec.rho2 != s0.rho2 ||
+            memcmp(&m.spec.eos, &s0.eos, sizeof(ofm_eos)) != 0)
+            return fail(ctx, OFM_EINVAL,
+                        "batched items must share ndim, precision, bc, eos, rho1, rho2, weno_eps and weno_order");
         if (bc == OFM_BC_PERIODIC && m.spec.n < 6) return fail(ctx, OFM_EINVAL, "periodic grids need n >= 6");
+        if (bc == OFM_BC_CHARACTERISTIC && m.spec.p_inf != s0.p_inf)
+            return fail(ctx, OFM_EINVAL, "batched items with the far-field boundary must share p_inf");
     }
     // tiling
     int maxn = 0;

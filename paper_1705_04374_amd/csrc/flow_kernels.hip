@@ -77,12 +77,14 @@ template <> struct Num<double> {
 template <typename T> struct Phys {
     T g1inv, dginv, pi1, dpi;
     T eps;             // (12/13) x the WENO epsilon (the indicators' scale in weno5_cell)
+    T eps3;            // the WENO epsilon (weno3_cell)
     T gam1, pc1, gam2, pc2;
     T rho1, rho2;      // reference phase densities (scale of the positivity checks)
+    T pfar;            // far-field pressure of the characteristic boundary
     __device__ __forceinline__ explicit Phys(const PhysD& d)
         : g1inv((T)d.g1inv), dginv((T)(d.g2inv - d.g1inv)), pi1((T)d.pi1), dpi((T)(d.pi2 - d.pi1)),
-          eps((T)(d.eps * (12.0 / 13.0))), gam1((T)d.gamma1), pc1((T)d.pc1), gam2((T)d.gamma2), pc2((T)d.pc2),
-          rho1((T)d.rho1), rho2((T)d.rho2) {}
+          eps((T)(d.eps * (12.0 / 13.0))), eps3((T)d.eps), gam1((T)d.gamma1), pc1((T)d.pc1), gam2((T)d.gamma2), pc2((T)d.pc2),
+          rho1((T)d.rho1), rho2((T)d.rho2), pfar((T)d.p_far) {}
     // mixture stiffened-gas coefficients under isobaric closure:
     // p = (E - rho|u|^2/2 - Pi(a2)) / Gamma(a2)
     __device__ __forceinline__ T gamma(T a2) const { return g1inv + a2 * dginv; }
@@ -93,6 +95,37 @@ __device__ __forceinline__ int bc_map(int i, int n, int bc)
 {
     if (bc == OFM_BC_PERIODIC) { i %= n; return i < 0 ? i + n : i; }
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// Characteristic far-field ghost (OFM_BC_CHARACTERISTIC): primitives w of
+// the nearest cell become those of a ghost outside the domain side (axis,
+// side = -1 low / +1 high).  The outgoing acoustic invariant p + side Z u_n
+// (Z = rho c, frozen sound speed) is kept and the incoming one
+// Rm = p - side Z u_n moves to Rm + beta (p_far - Rm), i.e. p += delta and
+// u_n -= side delta / Z with delta = beta (p_far - Rm) / 2.  beta = sigma h
+// with sigma = 0.25 on the unit domain relaxes the boundary towards p_far at
+// the rate sigma c (Poinsot and Lele's penalty at low Mach number).  A state
+// without a positive (rho c)^2 stays a zero-gradient copy.
+constexpr double kFarFieldSigma = 0.25;
+
+template <typename T, int ND>
+__device__ __forceinline__ void char_ghost(const Phys<T>& ph, T (&w)[4 + ND], int axis, int side, T beta)
+{
+    const T rho = w[0] + w[1];
+    const T a2 = w[3 + ND], p = w[2 + ND];
+    const T g = ph.gamma(a2);
+    const T a = rho * ((g + T(1)) * p + ph.pinf(a2));       // (rho c)^2 = a / g
+    if (!(a > T(0))) return;
+    const T Z = Num<T>::sqrt_ratio(a, g);
+    const T sZ = side > 0 ? Z : -Z;
+    T un = w[2];
+#pragma unroll
+    for (int m = 1; m < ND; ++m) un = axis == m ? w[2 + m] : un;
+    const T delta = T(0.5) * beta * (ph.pfar - Num<T>::fma(-sZ, un, p));
+    w[2 + ND] = p + delta;
+    const T du = delta * Num<T>::rcp(sZ);
+#pragma unroll
+    for (int m = 0; m < ND; ++m) w[2 + m] = axis == m ? w[2 + m] - du : w[2 + m];
 }
 
 // State -> primitive (a1r1, a2r2, u_1..u_d, p, a2); the energy slot holds Et.
@@ -162,10 +195,34 @@ __device__ __forceinline__ void weno5_cell(T a, T b, T c, T d, T e, T eps_s, T& 
     lo = Num<T>::fma(nl, sh * r, c);
 }
 
+// WENO3 (Jiang-Shu, candidate stencils (b, c) and (c, d), ideal weights 1/3
+// and 2/3 at the right edge, mirrored at the left) edge values of the centre
+// cell c, in the same difference form as weno5_cell: with B = b - c and
+// D = d - c the indicators are B^2 and D^2, the candidates c - B/2 and
+// c + D/2, the weights are normalised by the smaller (eps + beta) and the two
+// weight sums (in [1, 3] after scaling by 3) share one reciprocal.
+template <typename T>
+__device__ __forceinline__ void weno3_cell(T b, T c, T d, T eps, T& lo, T& hi)
+{
+    const T B = b - c, D = d - c;
+    const T eB = Num<T>::fma(B, B, eps), eD = Num<T>::fma(D, D, eps);
+    const T m = fmin(eB, eD);
+    const T rB = m * Num<T>::rcp(eB), rD = m * Num<T>::rcp(eD);
+    const T qB = rB * rB, qD = rD * rD;
+    // right edge: weights (qB, 2 qD) on (-B/2, D/2); left edge: (qD, 2 qB) on (-D/2, B/2)
+    const T nh = Num<T>::fma(T(2) * D, qD, -(B * qB)), nl = Num<T>::fma(T(2) * B, qB, -(D * qD));
+    const T sh = Num<T>::fma(T(2), qD, qB), sl = Num<T>::fma(T(2), qB, qD);
+    const T r = Num<T>::rcp(sh * sl) * T(0.5);
+    hi = Num<T>::fma(nh, sl * r, c);
+    lo = Num<T>::fma(nl, sh * r, c);
+}
+
 // Edges of one cell along one axis with the positivity / bounds checks.
 // Each partial density keeps its reconstruction only if it stays >= 0 at both
-// edges and at the interior Gauss-Lobatto point (12 mean - lo - hi)/10 that
-// keeps the cell mean (up to round_tol times the phase's reference density
+// edges and at the interior Gauss-Lobatto point that keeps the cell mean under
+// the rule exact for the reconstruction (WENO5: four points, the interior
+// value (12 mean - lo - hi)/10; WENO3: Simpson, (6 mean - lo - hi)/4)
+// (up to round_tol times the phase's reference density
 // or the largest magnitude of that partial density in the stencil);
 // a2 keeps its reconstruction only if it stays in [0, 1] at the same three
 // points (up to round_tol).  A variable that fails takes the cell value at
@@ -174,40 +231,48 @@ __device__ __forceinline__ void weno5_cell(T a, T b, T c, T d, T e, T eps_s, T& 
 // (Gamma+1) p + Pi <= 0, the whole cell is first order.
 //
 // The gas's partial density and volume fraction are exactly zero in pure
-// water, i.e. in most of a cloud's domain for the whole run.  WENO5 of a
+// water, i.e. in most of a cloud's domain for the whole run.  WENO of a
 // constant stencil returns the constant exactly, so where the stencils of a
 // whole wavefront are constant in those two variables their reconstruction
-// is skipped (same values, bit for bit).
-template <typename T, int ND>
+// is skipped (same values, bit for bit).  ORD = 5 or 3 (WENO3 reads s[1..3]).
+template <typename T, int ND, int ORD>
 __device__ __forceinline__ void cell_edges(const Phys<T>& ph, const T (&s)[5][4 + ND],
                                            T (&lo)[4 + ND], T (&hi)[4 + ND])
 {
+    static_assert(ORD == 5 || ORD == 3, "WENO order");
     constexpr int NV = 4 + ND;
+    constexpr int K0 = ORD == 5 ? 0 : 1, K1 = ORD == 5 ? 5 : 4;   // stencil cells read
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         if (v == 1 || v == NV - 1) {
             // constant stencil across the wavefront: the edges are the cell
             // value, which every check below would keep as well
-            const bool flat = s[0][v] == s[2][v] && s[1][v] == s[2][v] && s[3][v] == s[2][v] && s[4][v] == s[2][v];
+            const bool flat = (ORD == 3 || s[0][v] == s[2][v]) && s[1][v] == s[2][v] && s[3][v] == s[2][v] &&
+                              (ORD == 3 || s[4][v] == s[2][v]);
             if (__all(flat)) {
                 lo[v] = s[2][v];
                 hi[v] = s[2][v];
                 continue;
             }
         }
-        weno5_cell<T>(s[0][v], s[1][v], s[2][v], s[3][v], s[4][v], ph.eps, lo[v], hi[v]);
+        if (ORD == 5)
+            weno5_cell<T>(s[0][v], s[1][v], s[2][v], s[3][v], s[4][v], ph.eps, lo[v], hi[v]);
+        else
+            weno3_cell<T>(s[1][v], s[2][v], s[3][v], ph.eps3, lo[v], hi[v]);
         if (v < 2) {
             T big = v == 0 ? ph.rho1 : ph.rho2;
 #pragma unroll
-            for (int k = 0; k < 5; ++k) big = fmax(big, fabs(s[k][v]));
+            for (int k = K0; k < K1; ++k) big = fmax(big, fabs(s[k][v]));
             const T tol = -Num<T>::round_tol * big;
-            const T mid = (T(12) * s[2][v] - lo[v] - hi[v]) * T(0.1);
+            const T mid = ORD == 5 ? (T(12) * s[2][v] - lo[v] - hi[v]) * T(0.1)
+                                   : (T(6) * s[2][v] - lo[v] - hi[v]) * T(0.25);
             const bool keep = (lo[v] >= tol) && (hi[v] >= tol) && (mid >= tol);
             lo[v] = keep ? lo[v] : s[2][v];
             hi[v] = keep ? hi[v] : s[2][v];
         } else if (v == NV - 1) {
             const T lb = -Num<T>::round_tol, ub = T(1) + Num<T>::round_tol;
-            const T mid = (T(12) * s[2][v] - lo[v] - hi[v]) * T(0.1);
+            const T mid = ORD == 5 ? (T(12) * s[2][v] - lo[v] - hi[v]) * T(0.1)
+                                   : (T(6) * s[2][v] - lo[v] - hi[v]) * T(0.25);
             const bool keep = (lo[v] >= lb) && (lo[v] <= ub) && (hi[v] >= lb) && (hi[v] <= ub) && (mid >= lb) && (mid <= ub);
             lo[v] = keep ? lo[v] : s[2][v];
             hi[v] = keep ? hi[v] : s[2][v];
@@ -469,8 +534,8 @@ template <int TX, int TY> constexpr int stage_threads() { return round_up64(TX *
 template <typename T> constexpr int stage_waves_per_eu() { return sizeof(T) == 4 ? 3 : 1; }
 
 // RK stage STAGE = 0, 1, 2 (compiled separately: only the last carries the
-// reduction, only the first skips dU).
-template <typename T, int ND, int TX, int TY, int STAGE>
+// reduction, only the first skips dU); WENO order ORD = 5 or 3.
+template <typename T, int ND, int TX, int TY, int STAGE, int ORD>
 __global__ void __launch_bounds__((stage_threads<TX, TY>()))
 __attribute__((amdgpu_waves_per_eu(stage_waves_per_eu<T>())))
 stage_kernel(LaunchArgs a)
@@ -532,18 +597,25 @@ stage_kernel(LaunchArgs a)
     Red red;
     red.init();
 
+    const T beta = (T)(kFarFieldSigma * d.h);     // far-field relaxation fraction
     // load plane gz (with halo) into sW as primitives
     auto load_plane = [&](int gz) {
         const int64_t zoff = (int64_t)bc_map(gz, ND == 3 ? n : 1, bc) * plane;
         for (int e = tid; e < HX * HY; e += NT) {
             const int hy = e / HX, hx = e % HX;
-            const int cx = bc_map(x0 + hx - 3, n, bc);
-            const int cy = ND >= 2 ? bc_map(y0 + hy - 3, n, bc) : 0;
+            const int rx = x0 + hx - 3, ry = ND >= 2 ? y0 + hy - 3 : 0;
+            const int cx = bc_map(rx, n, bc);
+            const int cy = ND >= 2 ? bc_map(ry, n, bc) : 0;
             const int64_t idx = zoff + (int64_t)cy * n + cx;
             T q[NV], w[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) q[v] = ua[v * ncell + idx];
             to_prim<T, ND>(ph, q, w);
+            if (bc == OFM_BC_CHARACTERISTIC) {
+                // ghosts outside one domain side (corner ghosts are never read)
+                const bool ox = rx < 0 || rx >= n, oy = ND >= 2 && (ry < 0 || ry >= n);
+                if (ox != oy) char_ghost<T, ND>(ph, w, ox ? 0 : 1, (ox ? rx : ry) < 0 ? -1 : 1, beta);
+            }
 #pragma unroll
             for (int v = 0; v < NV; ++v) sW[(v * HY + hy) * HX + hx] = w[v];
         }
@@ -566,7 +638,7 @@ stage_kernel(LaunchArgs a)
             for (int k = 0; k < 5; ++k)
 #pragma unroll
                 for (int v = 0; v < NV; ++v) s[k][v] = sW[v * HY * HX + base + k * stride];
-            cell_edges<T, ND>(ph, s, lo, hi);
+            cell_edges<T, ND, ORD>(ph, s, lo, hi);
 #pragma unroll
             for (int v = 0; v < NV; ++v) { sEm[v * ES + e] = lo[v]; sEp[v * ES + e] = hi[v]; }
         }
@@ -710,9 +782,11 @@ stage_kernel(LaunchArgs a)
 #pragma unroll
                 for (int v = 0; v < NV; ++v) q[k][v] = q[k + 1][v];
             to_prim<T, ND>(ph, qn, q[4]);                          // planes p-1..p+3
+            if (bc == OFM_BC_CHARACTERISTIC && (p + 3 < 0 || p + 3 >= n))
+                char_ghost<T, ND>(ph, q[4], ND - 1, p + 3 < 0 ? -1 : 1, beta);
             if (p >= z0 - 2) {
                 T lo[NV], hi[NV];
-                cell_edges<T, ND>(ph, q, lo, hi);                  // cell p+1
+                cell_edges<T, ND, ORD>(ph, q, lo, hi);             // cell p+1
                 if (p >= z0 - 1) {
                     T fz[NV + 1];
                     hllc<T, ND, ND - 1>(ph, ep, lo, fz);           // face p+1/2
@@ -991,9 +1065,17 @@ template <typename T, int ND, int TX, int TY>
 static hipError_t launch_stage_t(const LaunchArgs& a, int stage, hipStream_t s)
 {
     const dim3 grid(a.n_work), block(stage_threads<TX, TY>());
-    if (stage == 0) hipLaunchKernelGGL((stage_kernel<T, ND, TX, TY, 0>), grid, block, 0, s, a);
-    else if (stage == 1) hipLaunchKernelGGL((stage_kernel<T, ND, TX, TY, 1>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((stage_kernel<T, ND, TX, TY, 2>), grid, block, 0, s, a);
+    if (a.ph.order == 3) {
+        if (stage == 0) hipLaunchKernelGGL((stage_kernel<T, ND, TX, TY, 0, 3>), grid, block, 0, s, a);
+        else if (stage == 1) hipLaunchKernelGGL((stage_kernel<T, ND, TX, TY, 1, 3>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((stage_kernel<T, ND, TX, TY, 2, 3>), grid, block, 0, s, a);
+    } else if (a.ph.order == 5) {
+        if (stage == 0) hipLaunchKernelGGL((stage_kernel<T, ND, TX, TY, 0, 5>), grid, block, 0, s, a);
+        else if (stage == 1) hipLaunchKernelGGL((stage_kernel<T, ND, TX, TY, 1, 5>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((stage_kernel<T, ND, TX, TY, 2, 5>), grid, block, 0, s, a);
+    } else {
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -17,6 +17,9 @@ struct PhysD {
     double gamma1, pc1, gamma2, pc2;
     double eps;        // WENO epsilon
     double rho1, rho2; // reference phase densities
+    double p_far;      // far-field pressure of the characteristic boundary
+    int32_t order;     // WENO order: 5 or 3
+    int32_t pad;
 };
 
 // Static description of one sample in a launch.

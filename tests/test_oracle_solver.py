@@ -157,6 +157,86 @@ def test_weno5_fifth_order_on_smooth_data():
 
 
 # --------------------------------------------------------------------------
+# WENO3 (Sec. 2.2: the paper's third-order option)
+# --------------------------------------------------------------------------
+
+def test_weno3_exact_for_linear_data_and_mirrored_left_edge():
+    rng = np.random.default_rng(12)
+    for _ in range(20):
+        a, b = rng.normal(size=2)
+        h = 0.1
+        v = [a + b * i * h for i in (-1, 0, 1)]       # cell averages of a + b x
+        assert abs(F.weno3_right_edge(*v, 1e-6) - (a + 0.5 * b * h)) < 1e-13 * (1 + abs(a))
+        assert abs(F.weno3_right_edge(*v[::-1], 1e-6) - (a - 0.5 * b * h)) < 1e-13 * (1 + abs(a))
+
+
+def test_weno3_ideal_weights_give_the_third_order_linear_scheme():
+    """With eps far above every indicator the weights are the ideal ones and
+    the edge value is that of the parabola with the three cell averages: exact
+    for quadratics."""
+    rng = np.random.default_rng(13)
+    for _ in range(20):
+        a, b, cc = rng.normal(size=3)
+        h = 0.1
+        avg = lambda i: a + b * i * h + cc * ((i * h) ** 2 + h * h / 12.0)
+        v = [avg(i) for i in (-1, 0, 1)]
+        exact = a + b * 0.5 * h + cc * (0.5 * h) ** 2
+        assert abs(F.weno3_right_edge(*v, 1e30) - exact) < 1e-12 * (1 + abs(exact))
+
+
+def test_weno3_third_order_on_smooth_data():
+    def err(n):
+        h = 1.0 / n
+        x0 = 0.3
+        f_avg = lambda i: (math.cos(2 * math.pi * (x0 + (i - 0.5) * h))
+                           - math.cos(2 * math.pi * (x0 + (i + 0.5) * h))) / (2 * math.pi * h)
+        v = [f_avg(i) for i in (-1, 0, 1)]
+        return abs(F.weno3_right_edge(*v, 1e-12) - math.sin(2 * math.pi * (x0 + 0.5 * h)))
+    assert math.log2(err(160) / err(320)) > 2.5
+
+
+def test_weno3_essentially_non_oscillatory_at_a_step():
+    """A jump between cells c and c+1: the right edge of c comes from the
+    smooth stencil (c-1, c), up to eps^2."""
+    assert abs(F.weno3_right_edge(0.0, 0.0, 1.0, 1e-6)) < 1e-11
+    assert abs(F.weno3_right_edge(1.0, 1.0, 0.0, 1e-6) - 1.0) < 1e-11
+
+
+def test_weno3_positivity_uses_the_simpson_point():
+    """A narrow dip in a partial density: both WENO3 edges are positive, but
+    with the cell mean they imply a negative value at the cell centre under
+    Simpson's rule, so the variable falls back to the cell value."""
+    c = cfg1d(8, weno_order=3)
+    w = lambda r: np.array([r, 0.0, 0.0, 1e5, 0.0])
+    st = [w(1.0), w(1.0), w(0.01), w(1.0), w(1.0)]
+    hi3 = F.weno3_right_edge(1.0, 0.01, 1.0, 1e-6)
+    assert hi3 > 0 and (6 * 0.01 - 2 * hi3) / 4 < 0        # edges > 0, Simpson point < 0
+    lo, hi, replaced = F.cell_edges(c, st)
+    assert replaced and lo[0] == 0.01 and hi[0] == 0.01
+    # a smooth positive stencil keeps its reconstruction
+    st = [w(1.0), w(1.1), w(1.2), w(1.3), w(1.4)]
+    lo, hi, replaced = F.cell_edges(c, st)
+    assert not replaced
+    assert abs(hi[0] - 1.25) < 1e-12 and abs(lo[0] - 1.15) < 1e-12
+    # the order follows the spec: curved data, WENO3 and WENO5 edges differ
+    st = [w(1.0 + 0.1 * k + 0.05 * k * k) for k in range(5)]
+    r = [x[0] for x in st]
+    lo, _, _ = F.cell_edges(c, st)
+    _, hi5, _ = F.cell_edges(cfg1d(8), st)
+    assert lo[0] == F.weno3_right_edge(r[3], r[2], r[1], 1e-6)
+    assert hi5[0] == F.weno5_right_edge(*r, 1e-6)
+    assert abs(lo[0] - F.weno5_right_edge(*r[::-1], 1e-6)) > 1e-4
+
+
+def test_weno3_shock_tube_converges_to_exact():
+    left, right, T, sl, sr = CASES["sod_ideal_gas"]
+    e1 = _tube(100, left, right, T, sl, sr, weno_order=3)
+    e2 = _tube(400, left, right, T, sl, sr, weno_order=3)
+    assert e2[0] < 0.6 * e1[0] and e2[1] < 0.6 * e1[1]
+    assert e2[0] < 0.015 and e2[1] < 0.015
+
+
+# --------------------------------------------------------------------------
 # HLLC (Sec. 2.2)
 # --------------------------------------------------------------------------
 
@@ -255,8 +335,8 @@ def test_exact_riemann_pinned_to_textbook():
     assert abs(ex.us - g["u_star"]) < 1e-5
 
 
-def _tube(n, left, right, T, sl, sr):
-    c = cfg1d(n)
+def _tube(n, left, right, T, sl, sr, **kw):
+    c = cfg1d(n, **kw)
     U = F.prim_to_cons(c, riemann_primitives(1, n, left, right))
     h = 1.0 / n
     t = 0.0
@@ -292,6 +372,126 @@ def test_shock_tube_converges_to_exact(case):
     e2 = _tube(400, left, right, T, sl, sr)
     assert e2[0] < 0.6 * e1[0] and e2[1] < 0.6 * e1[1]
     assert e2[0] < 0.01 and e2[1] < 0.01
+
+
+# --------------------------------------------------------------------------
+# Characteristic far-field boundary (Sec. 3.1, after Poinsot and Lele)
+# --------------------------------------------------------------------------
+
+def _water_impedance(p, rho=1000.0):
+    """rho c of pure water from the textbook stiffened-gas sound speed."""
+    return rho * math.sqrt(EOS["gamma1"] * (p + EOS["pc1"]) / rho)
+
+
+def test_char_ghost_keeps_outgoing_and_relaxes_incoming_invariant():
+    c = cfg1d(16, bc="characteristic")
+    rng = np.random.default_rng(21)
+    p_inf = c["p_inf"]
+    for _ in range(20):
+        p = rng.uniform(0.5, 2.0) * p_inf
+        u = rng.normal(0, 20.0)
+        w = np.array([1000.0, 0.0, u, p, 0.0])
+        Z = _water_impedance(p)
+        for side in (-1, 1):
+            assert np.array_equal(F.char_ghost(c, 0, side, 0.0, w), w)       # beta = 0: zero gradient
+            for beta in (0.3, 1.0):
+                g = F.char_ghost(c, 0, side, beta, w)
+                assert g[0] == w[0] and g[1] == w[1] and g[4] == w[4]
+                rp, rm = p + side * Z * u, p - side * Z * u
+                assert abs(g[3] + side * Z * g[2] - rp) <= 1e-12 * p_inf          # outgoing kept
+                assert abs(g[3] - side * Z * g[2] - (rm + beta * (p_inf - rm))) <= 1e-12 * p_inf
+    # the far field at rest is a fixed point; tangential velocity is copied
+    c2 = cfg_nd(2, 16, bc="characteristic")
+    w = np.array([1000.0, 0.0, 0.0, 3.0, p_inf, 0.0])
+    g = F.char_ghost(c2, 0, 1, 0.7, w)
+    assert g[2] == 0.0 and g[3] == 3.0 and g[4] == p_inf
+
+
+def test_char_boundary_rate_matches_linear_acoustics():
+    """Uniform water at rest with a small excess D over p_inf: only the two
+    boundary cells move, at the rates of the acoustic Riemann problem against
+    the ghost state: dp/dt = -c beta D / (2h), du/dt = s beta D / (2 rho h)
+    (outwards: s = -1 on the low side, +1 on the high side)
+    (beta = sigma h with sigma = 0.25), i.e. the incoming invariant relaxes at
+    K = sigma c.  The WENO epsilon is taken far below the squared jumps (the
+    ghost velocity is ~1e-6 m/s), so that the reconstruction keeps the two
+    constant states apart and the face sees exactly this Riemann problem."""
+    n = 32
+    c = cfg1d(n, bc="characteristic", weno_eps=1e-30)
+    p_inf = c["p_inf"]
+    D = 1e-4 * p_inf
+    W = np.zeros((5, n))
+    W[0], W[3] = 1000.0, p_inf + D
+    U = F.prim_to_cons(c, W)
+    L, _ = F.rhs(c, U)
+    h, beta = 1.0 / n, 0.25 / n
+    cs = _water_impedance(p_inf + D) / 1000.0
+    G = 1.0 / (EOS["gamma1"] - 1.0)
+    dpdt = L[3] / G                               # at rest, pure water: p = (Et)/Gamma
+    dudt = L[2] / 1000.0
+    assert np.all(L[:, 3:-3] == 0.0)
+    for i, side in ((0, -1), (n - 1, 1)):
+        assert abs(dpdt[i] / (-cs * beta * D / (2 * h)) - 1) < 2e-3
+        assert abs(dudt[i] / (side * beta * D / (2 * 1000.0 * h)) - 1) < 2e-3
+        assert abs(L[0, i]) > 0                   # mass leaves / enters with the wave
+
+
+def _run_to(c, W, T):
+    U = F.prim_to_cons(c, W)
+    t, h = 0.0, 1.0 / c["n"]
+    while t < T:
+        dt = min(0.3 * h / F.reduce(c, U)["s_max"], T - t)
+        U = F.step(c, U, dt)
+        t += dt
+    return F.cons_to_prim(c, U)
+
+
+def test_char_boundary_lets_an_acoustic_pulse_leave():
+    """A right-running pressure pulse (p' = Z u') leaves through the far-field
+    boundary: what stays in the domain after it has left is below 1.5 % of
+    its amplitude."""
+    n = 128
+    c = cfg1d(n, bc="characteristic")
+    p_inf = c["p_inf"]
+    Z = _water_impedance(p_inf)
+    x = (np.arange(n) + 0.5) / n
+    A = 1e5
+    dp = A * np.exp(-((x - 0.5) / 0.05) ** 2)
+    W = np.zeros((5, n))
+    W[0], W[2], W[3] = 1000.0, dp / Z, p_inf + dp
+    Wt = _run_to(c, W, 0.9 / (Z / 1000.0))
+    assert np.max(np.abs(Wt[3] - p_inf)) < 0.015 * A
+
+
+def test_char_boundary_relaxes_the_pressure_to_the_far_field():
+    """Water at rest 10 % above p_inf: the mean excess decays monotonically
+    under the far-field condition (below half after 4 L/c), while with
+    zero-gradient sides it stays."""
+    n = 64
+    W = np.zeros((5, n))
+    W[0], W[3] = 1000.0, 1.1e7
+    cl = _water_impedance(1.0e7) / 1000.0
+    devs = []
+    for T in (1.0, 2.0, 4.0):
+        Wt = _run_to(cfg1d(n, bc="characteristic"), W, T / cl)
+        devs.append(np.mean(Wt[3] - 1.0e7) / 1.0e6)
+    assert 1.0 > devs[0] > devs[1] > devs[2] and devs[2] < 0.5
+    Wz = _run_to(cfg1d(n), W, 1.0 / cl)
+    assert np.max(np.abs(Wz[3] / 1.1e7 - 1)) < 1e-13
+
+
+def test_char_boundary_keeps_mirror_symmetry():
+    """A centred bubble in 2-D: the far-field sides keep the solution
+    symmetric under x -> 1 - x and x <-> y."""
+    n = 24
+    c = cfg_nd(2, n, bc="characteristic", cloud_radius=0.2)
+    bub = np.array([[0.5, 0.5, 0.0, 0.12]])
+    U = F.init_state(c, bub)
+    U, _ = F.run_steps(c, U, 30)
+    W = F.cons_to_prim(c, U)
+    p = W[4].reshape(n, n)
+    assert np.max(np.abs(p - p[:, ::-1])) <= 1e-9 * np.max(np.abs(p))
+    assert np.max(np.abs(p - p.T)) <= 1e-9 * np.max(np.abs(p))
 
 
 # --------------------------------------------------------------------------
