@@ -56,23 +56,36 @@ class Fidelity:
 
 class Ledger:
     """JSON lines of every sample: term, index, QoIs, status, seconds.  An
-    existing ledger is read back on start (samples are not run again)."""
+    existing ledger is read back on start (samples are not run again).  A
+    solve whose pair partner is not done yet (the members of a pair may run
+    in different batches) enters as a member row (key "member": "f" or "c"),
+    so that a run stopped in between does not repeat it."""
 
     def __init__(self, path: str | None):
         self.path = path
         self.rows = {}
+        self.members = {}
         if path and os.path.exists(path):
             with open(path) as f:
                 for line in f:
                     r = json.loads(line)
-                    self.rows[(r["term"], r["index"])] = r
+                    if "member" in r:
+                        self.members[(r["term"], r["index"], r["member"])] = r
+                    else:
+                        self.rows[(r["term"], r["index"])] = r
 
     def have(self, term: int, index: int):
         return self.rows.get((term, index))
 
+    def have_member(self, term: int, index: int, which: str):
+        return self.members.get((term, index, which))
+
     def add(self, rows: list):
         for r in rows:
-            self.rows[(r["term"], r["index"])] = r
+            if "member" in r:
+                self.members[(r["term"], r["index"], r["member"])] = r
+            else:
+                self.rows[(r["term"], r["index"])] = r
         if self.path:
             with open(self.path, "a") as f:
                 for r in rows:
@@ -209,7 +222,7 @@ class OFMLMC:
             if m > 0:
                 idx = range(self.count[k], self.count[k] + m)
                 todo[k] = [i for i in idx if self.ledger.have(k, i) is None]
-        specs, bubs, where = [], [], []
+        specs, bubs, where, kept = [], [], [], []
         net_sets, net_where = [], []
         need = {}
         for k, idx in todo.items():
@@ -223,6 +236,8 @@ class OFMLMC:
                     if f.kind == "nn":
                         net_sets.append(b)
                         net_where.append((k, i, which))
+                    elif self.ledger.have_member(k, i, which) is not None:
+                        kept.append((k, i, which))
                     else:
                         specs.append(self.spec(f.n))
                         bubs.append(b)
@@ -256,10 +271,19 @@ class OFMLMC:
             for w, v in zip(net_where, vals):
                 got(w, dict(p_max=float(v), status=SAMPLE_OK, steps=0, x=(0.0, 0.0, 0.0), t_at_max=0.0), per)
             settle({(w[0], w[1]) for w in net_where})
+        if kept:
+            # solves of an earlier run whose partner was not done then
+            for w in kept:
+                m = self.ledger.have_member(*w)
+                got(w, m["q"], m["seconds"])
+            settle({(w[0], w[1]) for w in kept})
         if specs:
             def done(idx, qs, secs):
                 for j, q, s in zip(idx, qs, secs):
                     got(where[j], q, s)
+                # members still waiting for their partner
+                self.ledger.add([dict(term=where[j][0], index=where[j][1], member=where[j][2], q=q, seconds=s)
+                                 for j, q, s in zip(idx, qs, secs) if need[(where[j][0], where[j][1])] != 0])
                 settle({(where[j][0], where[j][1]) for j in idx})
             t0 = time.perf_counter()
             try:

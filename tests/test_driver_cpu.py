@@ -1,0 +1,63 @@
+"""Host logic of the OF-MLMC driver (no GPU): the ledger keeps the solves of
+a run stopped at its deadline, including pair members whose partner had not
+run yet, so that the resumed run solves only what is missing."""
+import json
+
+import pytest
+
+from paper_1705_04374_amd import driver
+from workloads.configs import MASTER_SEED, cloud_spec, solver_config
+
+
+def fake_qoi(spec, bubbles):
+    v = float(spec.n) * 1e6 + float(sum(sum(b) for b in bubbles))
+    return dict(p_max=v, x=(0.5, 0.5, 0.0), t_at_max=1e-4, t=2e-4, argmax=0, steps=spec.n, status=0,
+                p_sensor=v / 2, t_p_sensor=1e-4, gas_min=0.01, t_gas_min=1e-4, c_max=1500.0,
+                peak_distance=0.0)
+
+
+def make(tmp_path, log):
+    cfg = solver_config("cloud2d", 16)
+    return driver.OFMLMC(None, cfg, cloud_spec("cloud2d"), [16, 32], "f32", t_end=1e-4, seed=MASTER_SEED,
+                         ledger=str(tmp_path / "ledger.jsonl"), log=log)
+
+
+def test_stopped_run_keeps_unpaired_members(tmp_path, monkeypatch):
+    calls = []
+
+    def stop_after_fine(ctx, specs, bubbles, max_batch_bytes, log, deadline=None, done=None):
+        calls.append(sorted(s.n for s in specs))
+        big = [i for i, s in enumerate(specs) if s.n == 32]
+        done(big, [fake_qoi(specs[i], bubbles[i]) for i in big], [2.0] * len(big))
+        raise driver.Deadline("stop")
+
+    monkeypatch.setattr(driver, "solve_many", stop_after_fine)
+    mc = make(tmp_path, log=lambda *a: None)
+    with pytest.raises(driver.Deadline):
+        mc.sample_terms([3, 2])
+    # term 1 pairs (32, 16): only their fine members ran; nothing is settled
+    rows = [json.loads(l) for l in open(tmp_path / "ledger.jsonl")]
+    assert sorted((r["term"], r["index"], r["member"]) for r in rows) == [(1, 0, "f"), (1, 1, "f")]
+
+    seen = []
+
+    def run_rest(ctx, specs, bubbles, max_batch_bytes, log, deadline=None, done=None):
+        seen.append(sorted(s.n for s in specs))
+        done(list(range(len(specs))), [fake_qoi(s, b) for s, b in zip(specs, bubbles)], [1.0] * len(specs))
+
+    monkeypatch.setattr(driver, "solve_many", run_rest)
+    mc2 = make(tmp_path, log=lambda *a: None)
+    mc2.sample_terms([3, 2])
+    assert seen == [[16, 16, 16, 16, 16]]          # 3 term-0 solves + 2 coarse members, no fine again
+    assert mc2.count == [3, 2]
+    # the pairs carry the first run's fine QoIs and this run's coarse ones
+    for i in range(2):
+        r = mc2.ledger.have(1, i)
+        m = mc2.ledger.have_member(1, i, "f")
+        assert r["qf"] == m["q"]["p_max"] and r["seconds"] == 2.0 + 1.0 and r["ok"]
+        assert r["qc"] != r["qf"]
+    # a third driver finds everything in the ledger and solves nothing
+    monkeypatch.setattr(driver, "solve_many", lambda *a, **k: pytest.fail("solved again"))
+    mc3 = make(tmp_path, log=lambda *a: None)
+    mc3.sample_terms([3, 2])
+    assert mc3.q[1]["f"] == mc2.q[1]["f"] and mc3.q[0]["f"] == mc2.q[0]["f"]
