@@ -81,3 +81,35 @@ def test_two_level_2d_fp64_against_oracle_pipeline(tmp_path):
     assert mc2.solve_seconds == 0.0
     assert mc2.evaluate(W)["E"] == res["E"]
     ctx.close()
+
+
+def test_indicator_fit_with_one_finest_warmup_sample(tmp_path):
+    """App. A.1: one warm-up sample on the finest term, its variances inferred
+    from the lower terms' fit (Sec. 2.4.4 step 3); the driver's estimate
+    equals the oracle's fit + completion + estimator on the same QoIs."""
+    from paper_1705_04374_amd import capi
+    from paper_1705_04374_amd.driver import OFMLMC
+    ctx = capi.Context(0)
+    T = t_end("cloud2d")
+    spec = cloud_spec("cloud2d")
+    cfg = solver_config("cloud2d", 16)
+    mc = OFMLMC(ctx, cfg, spec, [16, 32, 64, 128], "f32", t_end=T, seed=MASTER_SEED, log=say)
+    say("fit warm-up")
+    mc.sample_terms([32, 16, 8, 1])
+    W = [1.0, 9.0, 72.0, 576.0]
+    r = mc.evaluate(W, fit=True)
+    assert r["fit_flag"] == 0 and r["M"] == [sum(mc.q[k]["ok"]) for k in range(4)] and r["M"][3] == 1
+    mom = [OM.term_moments(mc.q[k]["f"], mc.q[k]["c"] if k else None, mc.q[k]["ok"]) for k in range(4)]
+    v_ref, ok = OM.fit_indicators([m["M"] for m in mom], [m["Vf"] + m["Vc"] - 2 * m["C"] for m in mom], 1)
+    assert ok
+    np.testing.assert_allclose(r["v_hat"], v_ref, rtol=1e-12)
+    OM.infer_missing_terms(mom, v_ref, 1)
+    assert math.isclose(r["var_f"][3], mom[2]["Vf"], rel_tol=1e-12)
+    assert math.isclose(r["cov"][3], mom[3]["C"], rel_tol=1e-12)
+    a = OM.coefficients([m["Vf"] for m in mom], [m["Vc"] for m in mom], [m["C"] for m in mom], W)
+    np.testing.assert_allclose(r["alpha"], a, rtol=1e-10)
+    E = OM.estimate([m["mean_f"] for m in mom], [m["mean_c"] for m in mom], a)
+    assert math.isclose(r["E"], E, rel_tol=1e-10)
+    # without the fit the single finest sample has no variance
+    assert mc.evaluate(W)["var_f"][3] == 0.0
+    ctx.close()
