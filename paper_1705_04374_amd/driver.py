@@ -493,6 +493,56 @@ def train_level(ctx, cloud, cfg, n: int, count: int, t_end: float, seed: int, pr
     return sur, info
 
 
+def step_seconds(ctx, cfg: dict, cloud: dict, n: int, precision: str, seed: int, steps: int = 4) -> float:
+    """Wall seconds per time step of a single solve at grid n with the state
+    resident on the device (one sample at a time, as the plain Monte Carlo
+    comparator runs), after one warm-up step."""
+    import torch
+    from .state import alloc_state
+    c = dict(cfg)
+    c["n"] = n
+    spec = capi.make_spec(c, precision, n_steps=steps)
+    st, bufs = alloc_state(c, precision)
+    capi.ofm_state_init(ctx, spec, capi.ofm_sample_cloud(cloud, seed, 0, 0), st)
+    capi.ofm_step(ctx, spec, st, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    capi.ofm_step(ctx, spec, st, steps)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    del bufs
+    torch.cuda.empty_cache()
+    return sec
+
+
+def plain_mc_comparison(mc, res: dict, rel_tol: float, fp64_step_seconds: float, training: dict) -> dict:
+    """Plain Monte Carlo at the finest level to the same error, estimated as
+    the paper does (eq. (speedup), with the square): M = ceil(var / eps^2)
+    samples of the finest solve, var the sample variance of the finest
+    level's QoI (the fine members of the finest term), eps = rel_tol |E|;
+    each sample costs the finest grid's step count (mean of its solves) times
+    the measured FP64 time per step.  Against the OF-MLMC cost: the charged
+    time of its samples, plus the learned level's training solves and fit."""
+    L = mc.L
+    q = np.array([v for v, ok in zip(mc.q[L]["f"], mc.q[L]["ok"]) if ok], dtype=np.float64)
+    rows = [mc.ledger.have(L, i) for i in range(mc.count[L])]
+    steps = float(np.mean([r["steps_f"] for r in rows if r and r["ok"]]))
+    eps = rel_tol * abs(res["E"])
+    var = float(np.var(q, ddof=1)) if q.size >= 2 else float("nan")
+    m_mc = int(math.ceil(var / (eps * eps))) if q.size >= 2 else None
+    per = steps * fp64_step_seconds
+    of_cost = float(res["cost_seconds"])
+    train = float(training.get("solve_seconds_charged", 0.0)) + float(training.get("fit_seconds", 0.0))
+    out = dict(finest_samples=int(q.size), var_finest=var, eps=eps, M_mc=m_mc, steps_per_sample=steps,
+               fp64_step_seconds=fp64_step_seconds, seconds_per_sample=per,
+               mc_seconds=None if m_mc is None else m_mc * per,
+               ofmlmc_seconds=of_cost, training_seconds=train)
+    if m_mc is not None:
+        out["speedup"] = out["mc_seconds"] / (of_cost + train)
+        out["speedup_without_training"] = out["mc_seconds"] / of_cost
+    return out
+
+
 def variance_reduction(res: dict, term: int = 1) -> dict:
     """What the learned level gains on a pair term (solver level, network):
     the variance of the solver level alone against the pair term's variance
@@ -639,6 +689,9 @@ def _run_workload(a, w, ctx, cloud, T, seed, deadline, log) -> dict:
                      max_samples=[w["M_nn"]] + [None] * len(w["levels"]), fit=a.fit)
         out["ofmlmc"] = res
         out["variance_reduction"] = variance_reduction(res, 1)
+        sec = step_seconds(ctx, cfg, cloud, w["levels"][-1], "f64", seed)
+        out["plain_mc"] = plain_mc_comparison(mc, res, a.rel_tol, sec, sur.info)
+        log("plain FP64 MC at %d^3: %s" % (w["levels"][-1], json.dumps(out["plain_mc"])))
     return out
 
 

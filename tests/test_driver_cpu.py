@@ -61,3 +61,22 @@ def test_stopped_run_keeps_unpaired_members(tmp_path, monkeypatch):
     mc3 = make(tmp_path, log=lambda *a: None)
     mc3.sample_terms([3, 2])
     assert mc3.q[1]["f"] == mc2.q[1]["f"] and mc3.q[0]["f"] == mc2.q[0]["f"]
+
+
+def test_plain_mc_comparison_closed_form(tmp_path):
+    """eq. (speedup) with the square: M = ceil(var / eps^2) finest solves at
+    (steps x FP64 seconds per step) each, against the OF-MLMC cost plus the
+    learned level's training."""
+    mc = make(tmp_path, log=lambda *a: None)
+    mc.q[1] = dict(f=[1.0, 2.0, 3.0, 4.0, 99.0], c=[0.0] * 5, ok=[1, 1, 1, 1, 0])
+    mc.count = [0, 5]
+    mc.ledger.add([dict(term=1, index=i, qf=0.0, qc=0.0, ok=i < 4, steps_f=100 + 10 * i, steps_c=50,
+                        seconds=1.0) for i in range(5)])
+    r = driver.plain_mc_comparison(mc, dict(E=-100.0, cost_seconds=10.0), 0.01, 0.5,
+                                   dict(solve_seconds_charged=4.0, fit_seconds=6.0))
+    var = 5.0 / 3.0                                 # sample variance of 1, 2, 3, 4
+    assert r["finest_samples"] == 4 and abs(r["var_finest"] - var) < 1e-15
+    assert r["eps"] == 1.0 and r["M_mc"] == 2
+    assert r["steps_per_sample"] == 115.0 and r["seconds_per_sample"] == 57.5
+    assert r["mc_seconds"] == 115.0 and r["speedup"] == 115.0 / 20.0
+    assert r["speedup_without_training"] == 11.5
