@@ -360,6 +360,19 @@ int ofm_ofmlmc_optimal_M(ofm_ctx* ctx, int32_t L, const double* sig_t2, const do
                          const int64_t* M_have, int32_t mode, double target, int64_t* M_out,
                          int32_t* flag, void* stream);
 
+/* Moments of each term over the union of two disjoint sample sets (e.g. the
+ * samples of two GPUs): from each set's rows of ofm_mlmc_moments (M, means,
+ * unbiased variances and covariance; step 3 of the adaptive algorithm,
+ * Sec. 2.4.4), the pairwise update of Chan, Golub and LeVeque: the centred
+ * sums of squares and products add, plus M_a M_b / M times the product of
+ * the differences of the means.  It is the reduction an all-reduce of
+ * per-device moments applies; commutative, and associative up to rounding.
+ * a, b, out [dev] n_terms x 6 doubles each; out may equal a or b (in-place
+ * accumulation).  An empty set (M = 0) leaves the other unchanged.
+ * 1 <= n_terms <= 32.  Asynchronous. */
+int ofm_mlmc_merge_moments(ofm_ctx* ctx, int32_t n_terms, const double* a, const double* b, double* out,
+                           void* stream);
+
 /* Inferred variances of level differences (the optional part of step 3 of
  * the adaptive algorithm, Sec. 2.4.4; App. A.1): a weighted least-squares
  * line through ln V[q_l - q_{l-1}] (V = Var_f + Var_c - 2 Cov of the term's

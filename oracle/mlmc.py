@@ -48,6 +48,31 @@ def term_moments(qf, qc=None, ok=None) -> dict:
     return out
 
 
+def merge_moments(a: dict, b: dict) -> dict:
+    """Moments of one term over the union of two disjoint sample sets, from
+    each set's (M, means, unbiased variances and covariance): the pairwise
+    update of Chan, Golub and LeVeque, which adds to the two sets' centred
+    sums of squares (or products) the term M_a M_b / M delta_x delta_y of the
+    difference of their means.  This is what an all-reduce of per-GPU moments
+    would apply to combine sample shards."""
+    na, nb = a["M"], b["M"]
+    n = na + nb
+    if na == 0:
+        return dict(b)
+    if nb == 0:
+        return dict(a)
+    df = b["mean_f"] - a["mean_f"]
+    dc = b["mean_c"] - a["mean_c"]
+    w = na * nb / n
+    sff = a["Vf"] * (na - 1) + b["Vf"] * (nb - 1) + df * df * w
+    scc = a["Vc"] * (na - 1) + b["Vc"] * (nb - 1) + dc * dc * w
+    sfc = a["C"] * (na - 1) + b["C"] * (nb - 1) + df * dc * w
+    out = dict(M=n, mean_f=a["mean_f"] + df * nb / n, mean_c=a["mean_c"] + dc * nb / n, Vf=0.0, Vc=0.0, C=0.0)
+    if n >= 2:
+        out.update(Vf=sff / (n - 1), Vc=scc / (n - 1), C=sfc / (n - 1))
+    return out
+
+
 def coefficient_matrix(Vf, Vc, C, W):
     """Tridiagonal system of eq. (alpha-matvec) for alpha_0..alpha_{L-1}
     (alpha_L = 1).  Row k is d C(alpha) / d alpha_k = 0."""

@@ -28,7 +28,7 @@ EXPORTS = [
     "ofm_state_from_primitive", "ofm_state_to_conserved", "ofm_step", "ofm_solve", "ofm_solve_batch", "ofm_run_begin", "ofm_run_advance", "ofm_run_status", "ofm_run_destroy",
     "ofm_last_solve_stats",
     "ofm_mlmc_moments", "ofm_ofmlmc_coefficients", "ofm_ofmlmc_errors", "ofm_ofmlmc_estimate",
-    "ofm_ofmlmc_optimal_M", "ofm_ofmlmc_fit_indicators", "ofm_tune_set", "ofm_tune_get", "ofm_autotune", "ofm_kernel_timing", "ofm_kernel_times",
+    "ofm_ofmlmc_optimal_M", "ofm_ofmlmc_fit_indicators", "ofm_mlmc_merge_moments", "ofm_tune_set", "ofm_tune_get", "ofm_autotune", "ofm_kernel_timing", "ofm_kernel_times",
     "ofm_nn_create", "ofm_nn_destroy", "ofm_nn_param_count", "ofm_nn_get_params", "ofm_nn_set_params",
     "ofm_nn_set_normalization", "ofm_nn_reset_optimizer", "ofm_nn_features", "ofm_nn_forward", "ofm_nn_grads",
     "ofm_nn_train_step",
@@ -138,6 +138,7 @@ def lib():
         L.ofm_ofmlmc_estimate.argtypes = [vp, i32, vp, vp, vp, vp]
         L.ofm_ofmlmc_optimal_M.argtypes = [vp, i32, vp, vp, vp, i32, C.c_double, vp, vp, vp]
         L.ofm_ofmlmc_fit_indicators.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+        L.ofm_mlmc_merge_moments.argtypes = [vp, i32, vp, vp, vp, vp]
         L.ofm_tune_set.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32]
         L.ofm_tune_get.argtypes = [vp, i32, i32, i32, C.POINTER(TuneResult)]
         L.ofm_autotune.argtypes = [vp, C.POINTER(SolveSpec), C.POINTER(StateView), i32, C.POINTER(TuneResult),
@@ -373,6 +374,11 @@ def ofm_ofmlmc_estimate(ctx: Context, L: int, mom, alpha, E, stream=None):
 def ofm_ofmlmc_optimal_M(ctx: Context, L: int, sig, W, have, mode: int, target: float, out, flag, stream=None):
     ctx.check(lib().ofm_ofmlmc_optimal_M(ctx.h, L, _dptr(sig), _dptr(W), _dptr(have), mode, target, _dptr(out),
                                          _dptr(flag), _stream(stream)))
+
+
+def ofm_mlmc_merge_moments(ctx: Context, a, b, out, stream=None):
+    """a, b, out: [n_terms, 6] float64 device tensors (out may be a or b)."""
+    ctx.check(lib().ofm_mlmc_merge_moments(ctx.h, a.shape[0], _dptr(a), _dptr(b), _dptr(out), _stream(stream)))
 
 
 def ofm_ofmlmc_fit_indicators(ctx: Context, L: int, first: int, mom, v_hat, flag, stream=None):

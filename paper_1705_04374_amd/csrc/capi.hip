@@ -959,6 +959,17 @@ int ofm_ofmlmc_optimal_M(ofm_ctx* ctx, int32_t L, const double* sig, const doubl
     return OFM_OK;
 }
 
+int ofm_mlmc_merge_moments(ofm_ctx* ctx, int32_t n_terms, const double* a, const double* b, double* out,
+                           void* stream)
+{
+    if (!ctx) return fail(nullptr, OFM_EINVAL, "null context");
+    if (n_terms < 1 || n_terms > 32 || !a || !b || !out)
+        return fail(ctx, OFM_EINVAL, "ofm_mlmc_merge_moments: bad arguments");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, launch_merge(n_terms, a, b, out, (hipStream_t)stream));
+    return OFM_OK;
+}
+
 int ofm_ofmlmc_fit_indicators(ofm_ctx* ctx, int32_t L, int32_t first, double* mom, double* v_hat, int32_t* flag,
                               void* stream)
 {

@@ -204,6 +204,42 @@ __global__ void fit_kernel(int L, int first, double* mom, double* vhat, int32_t*
     *flag = 0;
 }
 
+// Moments of each term over the union of two disjoint sample sets
+// (pairwise update: the centred sums add, plus Ma Mb / M times the product of
+// the differences of the means); one thread per term.  out may be a or b.
+__global__ void merge_kernel(int n_terms, const double* a, const double* b, double* out)
+{
+    const int t = threadIdx.x;
+    if (t >= n_terms) return;
+    const double* x = a + 6 * t;
+    const double* y = b + 6 * t;
+    const double na = x[0], nb = y[0];
+    double r[6];
+    if (na == 0.0 || nb == 0.0) {
+        for (int k = 0; k < 6; ++k) r[k] = na == 0.0 ? y[k] : x[k];
+    } else {
+        const double n = na + nb;
+        const double df = y[1] - x[1], dc = y[2] - x[2];
+        const double w = na * nb / n;
+        const double sff = x[3] * (na - 1.0) + y[3] * (nb - 1.0) + df * df * w;
+        const double scc = x[4] * (na - 1.0) + y[4] * (nb - 1.0) + dc * dc * w;
+        const double sfc = x[5] * (na - 1.0) + y[5] * (nb - 1.0) + df * dc * w;
+        r[0] = n;
+        r[1] = x[1] + df * nb / n;
+        r[2] = x[2] + dc * nb / n;
+        r[3] = n >= 2.0 ? sff / (n - 1.0) : 0.0;
+        r[4] = n >= 2.0 ? scc / (n - 1.0) : 0.0;
+        r[5] = n >= 2.0 ? sfc / (n - 1.0) : 0.0;
+    }
+    for (int k = 0; k < 6; ++k) out[6 * t + k] = r[k];
+}
+
+hipError_t launch_merge(int n_terms, const double* a, const double* b, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(merge_kernel, dim3(1), dim3(64), 0, s, n_terms, a, b, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_fit(int L, int first, double* mom, double* vhat, int32_t* flag, hipStream_t s)
 {
     hipLaunchKernelGGL(fit_kernel, dim3(1), dim3(64), 0, s, L, first, mom, vhat, flag);

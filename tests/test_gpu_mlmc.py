@@ -145,3 +145,44 @@ def test_indicator_fit_needs_two_terms(ctx):
     assert torch.equal(mom, before)
     _, ok = O.fit_indicators([100, 50, 1], [2.0, 1.5, 0.0], 1)
     assert not ok
+
+
+def test_merged_shard_moments_match_the_whole(ctx):
+    """Per-shard moments merged on the device (the reduction of a per-GPU
+    all-reduce) equal the moments of all samples and the oracle's merge."""
+    import torch
+    from paper_1705_04374_amd import capi
+    L = 3
+    Ms = [9000, 700, 90, 12]
+    terms = toy_terms(L, Ms, 5)
+    whole = torch.zeros((L + 1, 6), dtype=torch.float64, device="cuda")
+    acc = torch.zeros((L + 1, 6), dtype=torch.float64, device="cuda")    # M = 0: empty
+    part = torch.zeros((L + 1, 6), dtype=torch.float64, device="cuda")
+    refs = [None] * (L + 1)
+    for l, (qf, qc, ok) in enumerate(terms):
+        tok = torch.tensor(ok, device="cuda")
+        capi.ofm_mlmc_moments(ctx, torch.tensor(qf, device="cuda"),
+                              torch.tensor(qc, device="cuda") if qc is not None else None, tok, whole[l])
+    # four shards of uneven sizes (one empty for the last term), merged in place
+    for s in range(4):
+        for l, (qf, qc, ok) in enumerate(terms):
+            cut = np.linspace(0, Ms[l], 5).astype(int)
+            lo, hi = cut[s], cut[s + 1]
+            if l == L and s == 2:
+                lo = hi
+            sl = slice(lo, hi)
+            if hi > lo:
+                capi.ofm_mlmc_moments(ctx, torch.tensor(qf[sl], device="cuda"),
+                                      torch.tensor(qc[sl], device="cuda") if qc is not None else None,
+                                      torch.tensor(ok[sl], device="cuda"), part[l])
+            else:
+                part[l].zero_()
+            r = O.term_moments(qf[sl], qc[sl] if qc is not None else None, ok[sl].astype(bool))
+            refs[l] = r if refs[l] is None else O.merge_moments(refs[l], r)
+        capi.ofm_mlmc_merge_moments(ctx, acc, part, acc)
+    got, want = acc.cpu().numpy(), whole.cpu().numpy()
+    assert np.array_equal(got[:, 0], want[:, 0])
+    np.testing.assert_allclose(got[:, 1:], want[:, 1:], rtol=1e-12, atol=0)
+    for l, r in enumerate(refs):
+        for j, k in ((1, "mean_f"), (2, "mean_c"), (3, "Vf"), (4, "Vc"), (5, "C")):
+            assert abs(got[l, j] - r[k]) <= 1e-12 * max(abs(r[k]), 1e-300), (l, k)

@@ -275,3 +275,33 @@ def test_inferred_finest_term_moments():
     assert m["Vf"] == m["Vc"] == 5.0e15
     assert math.isclose(m["Vf"] + m["Vc"] - 2 * m["C"], 1.2e14, rel_tol=1e-12)
     assert mom[1]["C"] == 4.3e15                       # measured terms untouched
+
+
+def test_merged_shard_moments_equal_the_moments_of_the_union():
+    """The pairwise update gives the two-pass moments of the concatenated
+    samples (to round-off), whatever the split, including empty and
+    single-sample shards; merging is commutative and associative."""
+    rng = np.random.default_rng(31)
+    qf = 5.0 + rng.normal(size=1000) * 3.0
+    qc = qf * 0.8 + rng.normal(size=1000)
+    whole = O.term_moments(qf, qc)
+    for cuts in ([0, 1000], [1, 999], [0, 0, 1000], [137, 400, 463], [500, 1, 499]):
+        edges = np.cumsum([0] + cuts)
+        parts = [O.term_moments(qf[a:b], qc[a:b]) for a, b in zip(edges[:-1], edges[1:])]
+        m = parts[0]
+        for p in parts[1:]:
+            m = O.merge_moments(m, p)
+        assert m["M"] == whole["M"]
+        for k in ("mean_f", "mean_c", "Vf", "Vc", "C"):
+            assert abs(m[k] - whole[k]) <= 1e-13 * abs(whole[k]), (cuts, k)
+    a, b, c = (O.term_moments(qf[i:j], qc[i:j]) for i, j in ((0, 300), (300, 310), (310, 1000)))
+    ab_c = O.merge_moments(O.merge_moments(a, b), c)
+    a_bc = O.merge_moments(a, O.merge_moments(b, c))
+    ba = O.merge_moments(b, a)
+    ab = O.merge_moments(a, b)
+    for k in ("mean_f", "Vf", "C"):
+        assert abs(ab_c[k] - a_bc[k]) <= 1e-13 * abs(whole[k])
+        assert abs(ab[k] - ba[k]) <= 1e-13 * abs(whole[k])
+    # two single samples: the variance of two values
+    one = O.merge_moments(O.term_moments([1.0], [2.0]), O.term_moments([4.0], [0.0]))
+    assert one["M"] == 2 and one["Vf"] == 4.5 and one["Vc"] == 2.0 and one["C"] == -3.0
