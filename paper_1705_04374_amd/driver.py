@@ -581,6 +581,9 @@ def main(argv=None):
     ap.add_argument("--max-iter", type=int, default=10)
     ap.add_argument("--fit", action="store_true",
                     help="one warm-up sample on the finest level, its variances inferred from the coarser levels")
+    ap.add_argument("--weno-order", type=int, default=5, choices=[3, 5], help="WENO reconstruction order")
+    ap.add_argument("--bc", default="zero_gradient", choices=["zero_gradient", "characteristic"],
+                    help="domain sides: zero gradient, or the characteristic far field with the p_inf penalty")
     ap.add_argument("--time-limit", type=float, default=0.0,
                     help="seconds; batches that would end later are not started (exit status 3, resume later)")
     a = ap.parse_args(argv)
@@ -610,14 +613,23 @@ def main(argv=None):
     return out
 
 
+def scheme(cfg: dict, a) -> dict:
+    """The solver options of the command line on a workload's configuration:
+    reconstruction order and boundary condition."""
+    cfg = dict(cfg)
+    cfg["weno_order"] = a.weno_order
+    cfg["bc"] = a.bc
+    return cfg
+
+
 def _run_workload(a, w, ctx, cloud, T, seed, deadline, log) -> dict:
     from workloads.configs import solver_config
-    out = dict(workload=a.workload, t_end=T, spec=w)
+    out = dict(workload=a.workload, t_end=T, spec=w, weno_order=a.weno_order, bc=a.bc)
     ledger = os.path.join(a.dir, "ledger_%s.jsonl" % a.workload)
     net_path = os.path.join(a.dir, "surrogate.npz")
     train_ledger = os.path.join(a.dir, "ledger_train.jsonl")
     if a.workload in ("mlmc2d", "batched3"):
-        cfg = solver_config(w["cloud"], w["levels"][0])
+        cfg = scheme(solver_config(w["cloud"], w["levels"][0]), a)
         mc = OFMLMC(ctx, cfg, cloud, w["levels"], w["precision"], t_end=T, seed=seed, ledger=ledger, log=log,
                     deadline=deadline)
         t0 = time.perf_counter()
@@ -658,7 +670,7 @@ def _run_workload(a, w, ctx, cloud, T, seed, deadline, log) -> dict:
             out["sequential_%s_seconds" % prec] = sum(solves[n] * single["%s_%d" % (prec, n)]["seconds"]
                                                       for n in w["levels"])
     elif a.workload == "surrogate":
-        cfg = solver_config(w["cloud"], w["n_train"])
+        cfg = scheme(solver_config(w["cloud"], w["n_train"]), a)
         sur, info = train_level(ctx, cloud, cfg, w["n_train"], w["count_train"], T, seed, w["precision"],
                                 log=log, epochs=a.epochs, ledger=train_ledger, deadline=deadline)
         save_surrogate(sur, net_path)
@@ -670,7 +682,7 @@ def _run_workload(a, w, ctx, cloud, T, seed, deadline, log) -> dict:
         out["ofmlmc"] = r
         out["variance_reduction"] = variance_reduction(r, 1)
     else:
-        cfg = solver_config(w["cloud"], w["levels"][0])
+        cfg = scheme(solver_config(w["cloud"], w["levels"][0]), a)
         if os.path.exists(net_path):
             sur = load_surrogate(ctx, cloud, net_path, seed=seed)
         else:
