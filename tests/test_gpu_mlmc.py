@@ -167,9 +167,9 @@ def test_merged_shard_moments_match_the_whole(ctx):
     for s in range(4):
         for l, (qf, qc, ok) in enumerate(terms):
             cut = np.linspace(0, Ms[l], 5).astype(int)
+            if l == L:
+                cut[2] = cut[3]                         # an empty third shard
             lo, hi = cut[s], cut[s + 1]
-            if l == L and s == 2:
-                lo = hi
             sl = slice(lo, hi)
             if hi > lo:
                 capi.ofm_mlmc_moments(ctx, torch.tensor(qf[sl], device="cuda"),
