@@ -80,3 +80,31 @@ def test_plain_mc_comparison_closed_form(tmp_path):
     assert r["steps_per_sample"] == 115.0 and r["seconds_per_sample"] == 57.5
     assert r["mc_seconds"] == 115.0 and r["speedup"] == 115.0 / 20.0
     assert r["speedup_without_training"] == 11.5
+
+
+def test_fit_warmup_takes_one_finest_sample(tmp_path, monkeypatch):
+    """eq. (warmup) counts, with a single finest sample when its variances
+    are to be inferred (App. A.1) and at least two solver differences lie
+    below it; without the fit every term keeps at least two."""
+    asked = []
+
+    def fake_solve(ctx, specs, bubbles, max_batch_bytes, log, deadline=None, done=None):
+        asked.append(sorted(s.n for s in specs))
+        done(list(range(len(specs))), [fake_qoi(s, b) for s, b in zip(specs, bubbles)], [1.0] * len(specs))
+
+    monkeypatch.setattr(driver, "solve_many", fake_solve)
+    cfg = solver_config("cloud2d", 16)
+    W_model = [1.0, 9.0, 72.0, 576.0]
+    for fit, last in ((True, 1), (False, 2)):
+        mc = driver.OFMLMC(None, cfg, cloud_spec("cloud2d"), [16, 32, 64, 128], "f32", t_end=1e-4,
+                           seed=MASTER_SEED, log=lambda *a: None)
+        seen = {}
+
+        def fake_eval(W, classical=False, qoi=None, fit=False, mc=mc):
+            seen["fit"] = fit
+            return dict(E=1.0, eps=0.0, alpha=[1.0] * 4, sigma_t2=[0.0] * 4)
+
+        monkeypatch.setattr(mc, "evaluate", fake_eval)
+        mc.run(rel_tol=0.01, W_model=W_model, fit=fit)
+        # W_L / W_l / 2^(L - l): 576/1/8 = 72, 576/9/4 = 16, 576/72/2 = 4, 1
+        assert mc.count == [72, 16, 4, last] and seen["fit"] is fit
