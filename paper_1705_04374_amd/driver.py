@@ -430,10 +430,12 @@ class OFMLMC:
             M, flag = self.allocate(res["sigma_t2"], W, tau)
             M = [min(m, c) if c else m for m, c in zip(M, cap)]
             target = [max(m, c) for m, c in zip(M, self.count)]
+            res["next_counts"] = target
             log("  next counts %s (allocation flag %d)" % (target, flag))
             if target == self.count:
                 break
         out = dict(history[-1])
+        out["converged"] = bool(out["eps"] <= out["tau"])
         out["history"] = history
         out["wall_seconds"] = time.perf_counter() - t_start
         out["fidelities"] = [repr(f) for f in self.fid]
@@ -521,8 +523,11 @@ def plain_mc_comparison(mc, res: dict, rel_tol: float, fp64_step_seconds: float,
     samples of the finest solve, var the sample variance of the finest
     level's QoI (the fine members of the finest term), eps = rel_tol |E|;
     each sample costs the finest grid's step count (mean of its solves) times
-    the measured FP64 time per step.  Against the OF-MLMC cost: the charged
-    time of its samples, plus the learned level's training solves and fit."""
+    the measured FP64 time per step.  Against the OF-MLMC cost to the same
+    error: the charged time of its samples if the run reached it, else the
+    cost of the allocation of eq. (M-tol) that the run ended with (its
+    counts times the measured cost per sample of each term); plus the
+    learned level's training solves and fit."""
     L = mc.L
     q = np.array([v for v, ok in zip(mc.q[L]["f"], mc.q[L]["ok"]) if ok], dtype=np.float64)
     rows = [mc.ledger.have(L, i) for i in range(mc.count[L])]
@@ -533,24 +538,32 @@ def plain_mc_comparison(mc, res: dict, rel_tol: float, fp64_step_seconds: float,
     per = steps * fp64_step_seconds
     of_cost = float(res["cost_seconds"])
     train = float(training.get("solve_seconds_charged", 0.0)) + float(training.get("fit_seconds", 0.0))
+    converged = bool(res["eps"] <= res.get("tau", eps))
+    nxt = res.get("next_counts")
+    to_tol = of_cost if converged or not nxt else float(sum(m * w for m, w in zip(nxt, res["W"])))
     out = dict(finest_samples=int(q.size), var_finest=var, eps=eps, M_mc=m_mc, steps_per_sample=steps,
                fp64_step_seconds=fp64_step_seconds, seconds_per_sample=per,
                mc_seconds=None if m_mc is None else m_mc * per,
-               ofmlmc_seconds=of_cost, training_seconds=train)
+               ofmlmc_converged=converged, ofmlmc_eps_reached=float(res["eps"]), ofmlmc_seconds_spent=of_cost,
+               ofmlmc_seconds=to_tol, ofmlmc_counts_to_tolerance=list(nxt) if (nxt and not converged) else None,
+               training_seconds=train)
     if m_mc is not None:
-        out["speedup"] = out["mc_seconds"] / (of_cost + train)
-        out["speedup_without_training"] = out["mc_seconds"] / of_cost
+        out["speedup"] = out["mc_seconds"] / (to_tol + train)
+        out["speedup_without_training"] = out["mc_seconds"] / to_tol
     return out
 
 
 def variance_reduction(res: dict, term: int = 1) -> dict:
     """What the learned level gains on a pair term (solver level, network):
-    the variance of the solver level alone against the pair term's variance
-    with the estimator's coefficient."""
+    the variance the term would have without the lower member, with the
+    same coefficient on the solver level (alpha_term^2 Var_f), against the
+    pair term's variance with the estimator's coefficients."""
     vf, vc, cv = res["var_f"][term], res["var_c"][term], res["cov"][term]
     st2 = res["sigma_t2"][term]
-    return dict(var_solver=vf, var_pair_term=st2, factor=vf / st2 if st2 > 0 else None,
-                alpha_nn=res["alpha"][term - 1],
+    a = res["alpha"][term]
+    alone = a * a * vf
+    return dict(var_solver=alone, var_pair_term=st2, factor=alone / st2 if st2 > 0 else None,
+                alpha_solver=a, alpha_nn=res["alpha"][term - 1],
                 correlation=cv / math.sqrt(vf * vc) if vf > 0 and vc > 0 else None)
 
 

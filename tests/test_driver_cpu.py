@@ -72,14 +72,20 @@ def test_plain_mc_comparison_closed_form(tmp_path):
     mc.count = [0, 5]
     mc.ledger.add([dict(term=1, index=i, qf=0.0, qc=0.0, ok=i < 4, steps_f=100 + 10 * i, steps_c=50,
                         seconds=1.0) for i in range(5)])
-    r = driver.plain_mc_comparison(mc, dict(E=-100.0, cost_seconds=10.0), 0.01, 0.5,
+    r = driver.plain_mc_comparison(mc, dict(E=-100.0, eps=0.9, tau=1.0, cost_seconds=10.0), 0.01, 0.5,
                                    dict(solve_seconds_charged=4.0, fit_seconds=6.0))
     var = 5.0 / 3.0                                 # sample variance of 1, 2, 3, 4
     assert r["finest_samples"] == 4 and abs(r["var_finest"] - var) < 1e-15
     assert r["eps"] == 1.0 and r["M_mc"] == 2
     assert r["steps_per_sample"] == 115.0 and r["seconds_per_sample"] == 57.5
     assert r["mc_seconds"] == 115.0 and r["speedup"] == 115.0 / 20.0
-    assert r["speedup_without_training"] == 11.5
+    assert r["speedup_without_training"] == 11.5 and r["ofmlmc_converged"]
+    # a run that stopped above the tolerance is charged the cost of the
+    # allocation it ended with (counts x measured cost per sample)
+    r = driver.plain_mc_comparison(mc, dict(E=-100.0, eps=2.0, tau=1.0, cost_seconds=10.0, next_counts=[8, 20],
+                                            W=[0.5, 2.0]), 0.01, 0.5, dict(solve_seconds_charged=4.0, fit_seconds=6.0))
+    assert not r["ofmlmc_converged"] and r["ofmlmc_seconds_spent"] == 10.0
+    assert r["ofmlmc_seconds"] == 44.0 and r["speedup"] == 115.0 / 54.0
 
 
 def test_fit_warmup_takes_one_finest_sample(tmp_path, monkeypatch):
