@@ -581,6 +581,10 @@ WORKLOADS = {
     # full OF-MLMC, learned level + 4 solver levels, to 1 % relative RMSE
     "ofmlmc": dict(cloud="cloud500", levels=[64, 128, 256, 512], n_train=64, count_train=4096, M_nn=65536,
                    precision="f32"),
+    # the same with 256^3 as the finest level; its terms are the first four
+    # terms of "ofmlmc" (same clouds), so the two share one ledger
+    "ofmlmc256": dict(cloud="cloud500", levels=[64, 128, 256], n_train=64, count_train=4096, M_nn=65536,
+                      precision="f32", ledger="ofmlmc"),
 }
 
 
@@ -638,7 +642,7 @@ def scheme(cfg: dict, a) -> dict:
 def _run_workload(a, w, ctx, cloud, T, seed, deadline, log) -> dict:
     from workloads.configs import solver_config
     out = dict(workload=a.workload, t_end=T, spec=w, weno_order=a.weno_order, bc=a.bc)
-    ledger = os.path.join(a.dir, "ledger_%s.jsonl" % a.workload)
+    ledger = os.path.join(a.dir, "ledger_%s.jsonl" % w.get("ledger", a.workload))
     net_path = os.path.join(a.dir, "surrogate.npz")
     train_ledger = os.path.join(a.dir, "ledger_train.jsonl")
     if a.workload in ("mlmc2d", "batched3"):
