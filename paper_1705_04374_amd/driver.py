@@ -596,6 +596,9 @@ def main(argv=None):
     ap.add_argument("--rel-tol", type=float, default=0.01)
     ap.add_argument("--epochs", type=int, default=600)
     ap.add_argument("--max-iter", type=int, default=10)
+    ap.add_argument("--min-samples", type=int, default=2,
+                    help="fewest samples of every term in the warm-up (the variances of a term with very few "
+                         "samples are unreliable, and the loop may stop on them)")
     ap.add_argument("--fit", action="store_true",
                     help="one warm-up sample on the finest level, its variances inferred from the coarser levels")
     ap.add_argument("--weno-order", type=int, default=5, choices=[3, 5], help="WENO reconstruction order")
@@ -714,7 +717,7 @@ def _run_workload(a, w, ctx, cloud, T, seed, deadline, log) -> dict:
         d = cfg["ndim"]
         single = [1e-6] + [float(n) ** (d + 1) for n in w["levels"]]
         W_model = [single[0], single[1]] + [single[k] + single[k - 1] for k in range(2, len(single))]
-        res = mc.run(rel_tol=a.rel_tol, W_model=W_model, max_iter=a.max_iter,
+        res = mc.run(rel_tol=a.rel_tol, W_model=W_model, max_iter=a.max_iter, min_samples=a.min_samples,
                      max_samples=[w["M_nn"]] + [None] * len(w["levels"]), fit=a.fit)
         out["ofmlmc"] = res
         out["variance_reduction"] = variance_reduction(res, 1)
