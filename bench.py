@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 side measurement")
     ap.add_argument("--no-weno3", action="store_true", help="skip the WENO3 side measurement")
+    ap.add_argument("--nn", action="store_true",
+                    help="instead: forward pass of the learned level over 65 536 sets of 500 bubbles (one JSON line)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-tune", action="store_true", help="use the default tile instead of autotuning")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -121,6 +123,60 @@ def measure(ctx, capi, cfg, bub, precision, steps, warmup, tune=True):
     del bufs
     torch.cuda.empty_cache()
     return dict(wall=wall, q=q, kt=kt, tuned=tuned)
+
+
+def nn_bench(a):
+    """The learned level's inference at the scale of its OF-MLMC term: the
+    set network's forward over 65 536 sets of 500 bubbles (features of 256
+    sampled clouds, repeated), timed with events on the stream it runs on.
+    Algorithmic flops per bubble row: the 4 -> 128 input layer (2 x 4 x 128)
+    and the 128 x 128 layer on the matrix cores (2 x 128 x 128); the per-set
+    head (2 x 128 x 128 + 2 x 128 x 5) is counted per set.  Roofline: dense
+    BF16 matrix-core peak."""
+    import numpy as np
+    import torch
+    from paper_1705_04374_amd import capi
+    from workloads.configs import MASTER_SEED, cloud_spec
+    cloud = cloud_spec("cloud500")
+    ctx = capi.Context(0)
+    n_sets, n_distinct = 65536, 256
+    bub = [capi.ofm_sample_cloud(cloud, MASTER_SEED, 3, i) for i in range(n_distinct)]
+    nb = cloud["n_bubbles"]
+    b = torch.tensor(np.concatenate(bub), dtype=torch.float64, device="cuda")
+    x0 = torch.empty((b.shape[0], 4), dtype=torch.float32, device="cuda")
+    capi.ofm_nn_features(cloud, b, x0)
+    x = x0.repeat(n_sets // n_distinct, 1).contiguous()
+    off = torch.arange(0, (n_sets + 1) * nb, nb, dtype=torch.int32, device="cuda")
+    y = torch.empty((n_sets, 5), dtype=torch.float32, device="cuda")
+    net = capi.SetNet(ctx, 1.0 / nb, seed=MASTER_SEED)
+    for _ in range(max(a.warmup, 1)):
+        net.forward(x, off, y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(a.steps, 1)
+    e0.record()
+    for _ in range(reps):
+        net.forward(x, off, y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    rows = n_sets * nb
+    flops = rows * (2 * 4 * 128 + 2 * 128 * 128) + n_sets * (2 * 128 * 128 + 2 * 128 * 5)
+    tfl = flops / (ms * 1e-3) / 1e12
+    assert bool(torch.isfinite(y).all())
+    net.close()
+    ctx.close()
+    return {
+        "metric": "learned-level forward: sets/s (65 536 sets of 500 bubbles)",
+        "value": n_sets / (ms * 1e-3), "unit": "sets/s", "n_gpus": 1, "steps": reps, "warmup": max(a.warmup, 1),
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic (features of 256 seeded 500-bubble clouds, repeated)",
+        "config": {"workload": "set network 4-128-128 / sum pool / 128-128-5 forward, 65536 sets x 500 bubbles",
+                   "rows": rows},
+        "roofline": {"kernel": "ofm_nn_forward (phi_pool_kernel + head)", "bound": "mfma", "achieved": round(tfl, 2),
+                     "peak": 2500.0, "unit": "TFLOP/s", "frac": round(tfl / 2500.0, 4), "traffic": None,
+                     "algorithmic_flops_per_call": flops},
+    }
 
 
 def cpu_baseline(cfg, bub):
@@ -171,6 +227,9 @@ def main():
               "(samples would shard across GPUs with one small all-reduce per OF-MLMC iteration; "
               "see the design notes). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if a.nn:
+        print(json.dumps(nn_bench(a)), flush=True)
+        return
     import torch
     from paper_1705_04374_amd import capi
     from workloads.configs import MASTER_SEED, cloud_spec, solver_config

@@ -144,14 +144,17 @@ __global__ void __launch_bounds__(256) gemm_finish_kernel(const float* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Fused per-set forward of phi and the sum pool: one workgroup per set.
-// Rows of the set are processed 128 at a time: the input layer on the
-// vector units into LDS (bf16), the 128 x 128 layer on the matrix cores,
-// bias + ReLU, then column sums over the rows (fixed order).
+// Fused per-set forward of phi and the sum pool.  A workgroup stages the
+// weights in LDS once and then takes sets gridDim.x apart.  Rows of a set
+// are processed 128 at a time: the input layer on the vector units into LDS
+// (bf16), the 128 x 128 layer on the matrix cores, bias + ReLU, then column
+// sums over the rows (fixed order, so a set's result does not depend on the
+// grid).
 // ---------------------------------------------------------------------------
 constexpr int HP = 128 + 8;
 
 __global__ void __launch_bounds__(256) phi_pool_kernel(const float* __restrict__ x, const int32_t* __restrict__ offsets,
+                                                       int n_sets,
                                                        const float* __restrict__ P, const uint16_t* __restrict__ W2bf,
                                                        float pool_scale, float* __restrict__ s_out,
                                                        uint16_t* __restrict__ s_bf, uint16_t* __restrict__ h1_bf,
@@ -161,85 +164,86 @@ __global__ void __launch_bounds__(256) phi_pool_kernel(const float* __restrict__
     __shared__ uint16_t sH[128 * HP];   // h1 chunk [row][k]
     __shared__ float sW1[128 * 4], sb1[128], sb2[128];
     __shared__ float colsum[2][128];
-    const int set = blockIdx.x;
-    const int r0 = offsets[set], r1 = offsets[set + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const float* W1 = P + NN_W1;
     for (int e = tid; e < 128 * 128; e += 256) sW[(e >> 7) * HP + (e & 127)] = W2bf[e];
     for (int e = tid; e < 128 * 4; e += 256) sW1[e] = W1[e];
     if (tid < 128) { sb1[tid] = P[NN_B1 + tid]; sb2[tid] = P[NN_B2 + tid]; }
-    float acc_col = 0.f;   // running column sum, thread tid < 128 owns column tid
-    for (int c0 = r0; c0 < r1; c0 += 128) {
-        __syncthreads();
-        // input layer: thread -> row tid / 2, 64 columns
-        {
-            const int rl = tid >> 1, cb = (tid & 1) * 64;
-            const int r = c0 + rl;
-            float xv[4] = { 0.f, 0.f, 0.f, 0.f };
-            if (r < r1) {
+    for (int set = blockIdx.x; set < n_sets; set += gridDim.x) {
+        const int r0 = offsets[set], r1 = offsets[set + 1];
+        float acc_col = 0.f;   // running column sum, thread tid < 128 owns column tid
+        for (int c0 = r0; c0 < r1; c0 += 128) {
+            __syncthreads();
+            // input layer: thread -> row tid / 2, 64 columns
+            {
+                const int rl = tid >> 1, cb = (tid & 1) * 64;
+                const int r = c0 + rl;
+                float xv[4] = { 0.f, 0.f, 0.f, 0.f };
+                if (r < r1) {
 #pragma unroll
-                for (int k = 0; k < 4; ++k) xv[k] = x[(int64_t)r * 4 + k];
+                    for (int k = 0; k < 4; ++k) xv[k] = x[(int64_t)r * 4 + k];
+                }
+                for (int c = cb; c < cb + 64; ++c) {
+                    float z = sb1[c];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) z += xv[k] * sW1[c * 4 + k];
+                    const uint16_t h = r < r1 ? to_bf16(fmaxf(z, 0.f)) : (uint16_t)0;
+                    sH[rl * HP + c] = h;
+                    if (h1_bf && r < r1) h1_bf[(int64_t)r * 128 + c] = h;
+                }
             }
-            for (int c = cb; c < cb + 64; ++c) {
-                float z = sb1[c];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) z += xv[k] * sW1[c * 4 + k];
-                const uint16_t h = r < r1 ? to_bf16(fmaxf(z, 0.f)) : (uint16_t)0;
-                sH[rl * HP + c] = h;
-                if (h1_bf && r < r1) h1_bf[(int64_t)r * 128 + c] = h;
-            }
-        }
-        __syncthreads();
-        floatx16 acc[2][2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
-#pragma unroll
-        for (int k16 = 0; k16 < 128; k16 += 16) {
-            const int kk = k16 + (lane >> 5) * 8;
-            bf16x8 a[2], b[2];
-#pragma unroll
-            for (int i = 0; i < 2; ++i) a[i] = frag(&sH[(wr * 64 + i * 32 + (lane & 31)) * HP + kk]);
-#pragma unroll
-            for (int j = 0; j < 2; ++j) b[j] = frag(&sW[(wc * 64 + j * 32 + (lane & 31)) * HP + kk]);
+            __syncthreads();
+            floatx16 acc[2][2];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-        }
-        // bias + ReLU + per-column partial sums of this wave's 64 rows
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int col = wc * 64 + j * 32 + (lane & 31);
-            const float bb = sb2[col];
-            float cs = 0.f;
+                    for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int k16 = 0; k16 < 128; k16 += 16) {
+                const int kk = k16 + (lane >> 5) * 8;
+                bf16x8 a[2], b[2];
 #pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    const int rl = wr * 64 + i * 32 + mfma_row(e, lane);
-                    const int r = c0 + rl;
-                    const float z = acc[i][j][e] + bb;
-                    if (r < r1) {
-                        cs += fmaxf(z, 0.f);
-                        if (z2_out) z2_out[(int64_t)r * 128 + col] = z;
+                for (int i = 0; i < 2; ++i) a[i] = frag(&sH[(wr * 64 + i * 32 + (lane & 31)) * HP + kk]);
+#pragma unroll
+                for (int j = 0; j < 2; ++j) b[j] = frag(&sW[(wc * 64 + j * 32 + (lane & 31)) * HP + kk]);
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+            }
+            // bias + ReLU + per-column partial sums of this wave's 64 rows
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int col = wc * 64 + j * 32 + (lane & 31);
+                const float bb = sb2[col];
+                float cs = 0.f;
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        const int rl = wr * 64 + i * 32 + mfma_row(e, lane);
+                        const int r = c0 + rl;
+                        const float z = acc[i][j][e] + bb;
+                        if (r < r1) {
+                            cs += fmaxf(z, 0.f);
+                            if (z2_out) z2_out[(int64_t)r * 128 + col] = z;
+                        }
                     }
-                }
-            cs += __shfl_xor(cs, 32, 64);
-            if (lane < 32) colsum[wr][col] = cs;
+                cs += __shfl_xor(cs, 32, 64);
+                if (lane < 32) colsum[wr][col] = cs;
+            }
+            __syncthreads();
+            if (tid < 128) acc_col += colsum[0][tid] + colsum[1][tid];
         }
-        __syncthreads();
-        if (tid < 128) acc_col += colsum[0][tid] + colsum[1][tid];
-    }
-    if (tid < 128) {
-        const float sv = pool_scale * acc_col;
-        s_out[(int64_t)set * 128 + tid] = sv;
-        s_bf[(int64_t)set * 128 + tid] = to_bf16(sv);
+        if (tid < 128) {
+            const float sv = pool_scale * acc_col;
+            s_out[(int64_t)set * 128 + tid] = sv;
+            s_bf[(int64_t)set * 128 + tid] = to_bf16(sv);
+        }
     }
 }
 
@@ -493,8 +497,11 @@ hipError_t nn_gemm_finish(const float* C, int splits, int64_t M, int N, int mode
 hipError_t nn_phi_pool(const float* x, const int32_t* offsets, int n_sets, const float* P, const uint16_t* W2bf,
                        float pool_scale, float* s_out, uint16_t* s_bf, uint16_t* h1_bf, float* z2, hipStream_t st)
 {
-    hipLaunchKernelGGL(phi_pool_kernel, dim3(n_sets), dim3(256), 0, st, x, offsets, P, W2bf, pool_scale, s_out, s_bf,
-                       h1_bf, z2);
+    // two resident workgroups per CU (73.7 KB of LDS each): a few rounds of
+    // them, each taking sets gridDim.x apart
+    const int grid = n_sets < 4096 ? n_sets : 4096;
+    hipLaunchKernelGGL(phi_pool_kernel, dim3(grid), dim3(256), 0, st, x, offsets, n_sets, P, W2bf, pool_scale, s_out,
+                       s_bf, h1_bf, z2);
     return hipGetLastError();
 }
 

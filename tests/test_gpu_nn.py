@@ -159,3 +159,29 @@ def test_training_learns_a_set_function(ctx):
     last = loss.item()
     say("  loss", first, "->", last)
     assert last < 0.1 * first
+
+
+def test_forward_of_many_sets_is_per_set(ctx):
+    """More sets than workgroups (each workgroup then takes several sets):
+    every set's output equals the one computed in a small batch, bit for
+    bit, and a sample of them matches the oracle."""
+    import torch
+    say("nn forward, many sets")
+    rng = np.random.default_rng(5)
+    sizes = rng.integers(0, 300, size=9000)
+    sizes[:3] = [500, 0, 129]
+    p, x, off, _ = problem(2, list(sizes))
+    net = gpu_net(ctx, p, 1.0 / 500)
+    y = torch.empty((len(sizes), 5), dtype=torch.float32, device="cuda")
+    net.forward(dev(x), dev(off), y)
+    got = y.cpu().numpy()
+    for lo in (0, 4096, 8990):
+        hi = min(lo + 10, len(sizes))
+        xs = x[off[lo]:off[hi]]
+        offs = off[lo:hi + 1] - off[lo]
+        ys = torch.empty((hi - lo, 5), dtype=torch.float32, device="cuda")
+        net.forward(dev(xs), dev(offs), ys)
+        assert np.array_equal(ys.cpu().numpy(), got[lo:hi]), lo
+        ref, _ = N.forward(p, xs, offs, 1.0 / 500, bf16_ops=True)
+        assert rel(got[lo:hi].astype(np.float64), ref) <= 1e-3
+    assert np.all(np.isfinite(got))
