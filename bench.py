@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--cloud", default="cloud500", choices=["cloud500", "cloud50"],
+                    help="cloud of the solve (cloud50: 50 bubbles in a ball of 0.25)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 side measurement")
     ap.add_argument("--no-weno3", action="store_true", help="skip the WENO3 side measurement")
     ap.add_argument("--nn", action="store_true",
@@ -244,8 +246,8 @@ def main():
         del x, y
         torch.cuda.empty_cache()
     n = a.n
-    cfg = solver_config("cloud500", n)
-    bub = capi.ofm_sample_cloud(cloud_spec("cloud500"), MASTER_SEED, 0, 0)
+    cfg = solver_config(a.cloud, n)
+    bub = capi.ofm_sample_cloud(cloud_spec(a.cloud), MASTER_SEED, 0, 0)
     ctx = capi.Context(0)
     cells = n ** 3
     r = measure(ctx, capi, cfg, bub, a.precision, a.steps, a.warmup, tune=not a.no_tune)
@@ -294,8 +296,8 @@ def main():
         "vs_baseline": None,
         "dtype": a.precision,
         "data": "synthetic (seeded 500-bubble cloud, no dataset)",
-        "config": {"workload": "cloud500 single solve, %d^3, %s stencil, FP64 QoI/dt" % (n, a.precision),
-                   "cells": cells, "bubbles": 500, "status": r["q"]["status"], "steps_taken": r["q"]["steps"]},
+        "config": {"workload": "%s single solve, %d^3, %s stencil, FP64 QoI/dt" % (a.cloud, n, a.precision),
+                   "cells": cells, "bubbles": cloud_spec(a.cloud)["n_bubbles"], "status": r["q"]["status"], "steps_taken": r["q"]["steps"]},
         "roofline": roof,
     }
     if not a.no_fp64 and a.precision == "f32":
