@@ -14,8 +14,7 @@ struct TileChoice {
 
 struct Tuning {
     // key: (precision, ndim, size class = ceil(log2 n)); the WENO order and
-    // the boundary condition share an entry (same data movement, so the
-    // same tile suits both)
+    // the boundary condition share an entry (the last autotune wins)
     std::map<std::tuple<int, int, int>, TileChoice> table;
 
     static int size_class(int n)
