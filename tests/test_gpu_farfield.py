@@ -126,3 +126,25 @@ def test_farfield_batch_needs_one_far_field_pressure(ctx):
     assert e.value.code == capi.OFM_EINVAL
     qa = capi.ofm_solve_batch(ctx, [a, a], [bub, bub])
     assert qa[0] == qa[1] == capi.ofm_solve(ctx, a, bub)
+
+
+def test_farfield_weno3_batch_equals_single_solves(ctx):
+    """The options in the batched path: samples of different sizes with the
+    far-field boundary and WENO3, advanced in the same launches, give the
+    QoIs of their single solves bit for bit."""
+    from paper_1705_04374_amd import capi
+    say("far field + weno3 batch")
+    T = 6.0e-4
+    specs, bubs = [], []
+    for i, n in enumerate([32, 16, 24, 32]):
+        cfg = far("cloud2d", n)
+        cfg["weno_order"] = 3
+        specs.append(capi.make_spec(cfg, "f64", t_end=T))
+        bubs.append(sample_cloud(cloud_spec("cloud2d"), MASTER_SEED, 2, i))
+    qb = capi.ofm_solve_batch(ctx, specs, bubs)
+    for s, b, q in zip(specs, bubs, qb):
+        assert capi.ofm_solve(ctx, s, b) == q
+    cfg = far("cloud2d", 24)
+    cfg["weno_order"] = 3
+    ref = OF.solve(cfg, bubs[2], t_end=T)
+    assert math.isclose(qb[2]["p_max"], ref["p_max"], rel_tol=1e-9) and qb[2]["steps"] == ref["steps"]
