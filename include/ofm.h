@@ -381,9 +381,11 @@ int ofm_mlmc_merge_moments(ofm_ctx* ctx, int32_t n_terms, const double* a, const
  * of a sample variance of Gaussian data is 2/(M - 1)).
  * mom [dev] (L+1) x 6 as written by ofm_mlmc_moments: the terms
  * l >= max(first, 1) with fewer than two samples (e.g. a single finest
- * warm-up sample) are completed in place: both members take the variance of
- * level l-1 (term l-1's fine variance) and the covariance is set so that
- * Var_f + Var_c - 2 Cov equals the inferred value.  v_hat [dev] L+1 doubles:
+ * warm-up sample) are completed in place: the coarse member takes the
+ * variance of level l-1 (term l-1's fine variance), the members'
+ * correlation is term l-1's, and the fine variance is set so that
+ * Var_f + Var_c - 2 Cov equals the inferred value (a valid covariance; at
+ * least (1 - rho^2) Var_c).  v_hat [dev] L+1 doubles:
  * exp of the fitted line for l = first..L, 0 below.  flag [dev] 1 int: 0, or
  * OFM_ESINGULAR when fewer than two terms qualify (then v_hat is 0 and mom
  * unchanged).  1 <= L <= 31, 0 <= first <= L.  Asynchronous. */

@@ -201,18 +201,27 @@ def fit_indicators(M, Vdiff, first: int = 1):
 
 def infer_missing_terms(mom: list, v_hat, first: int = 1):
     """Moments of the terms l >= max(first, 1) that have fewer than two
-    samples (the single finest warm-up sample of App. A.1), from the fit:
-    both members take the variance of level l-1 (term l-1's fine members,
-    the closest measured level) and the covariance follows from the inferred
-    difference variance, C = (Vf + Vc - v_hat) / 2 (V[a - b] = Va + Vb - 2C).
+    samples (the single finest warm-up sample of App. A.1), from the fit.
+    The coarse member is level l-1, whose variance term l-1 measured
+    (Vc = its Vf); the correlation of the members is taken from term l-1
+    (rho = C / sqrt(Vf Vc) there, 0 if undefined); the fine member's
+    standard deviation s then solves s^2 + Vc - 2 rho s sqrt(Vc) = v_hat
+    (V[a - b] = Va + Vb - 2 Cov), the larger root, so that the completed
+    moments are a valid covariance whose difference variance is v_hat
+    (when v_hat < (1 - rho^2) Vc, the smallest such value, s = rho sqrt(Vc)).
     mom: list of term_moments dicts, updated in place."""
     for l in range(max(first, 1), len(mom)):
         if mom[l]["M"] >= 2:
             continue
-        v = mom[l - 1]["Vf"]
-        mom[l]["Vf"] = v
-        mom[l]["Vc"] = v
-        mom[l]["C"] = (v + v - v_hat[l]) / 2.0
+        a, b, c = mom[l - 1]["Vf"], mom[l - 1]["Vc"], mom[l - 1]["C"]
+        rho = c / math.sqrt(a * b) if a > 0 and b > 0 else 0.0
+        rho = min(max(rho, -1.0), 1.0)
+        vc = a
+        sc = math.sqrt(vc)
+        s = max(rho * sc + math.sqrt(max(v_hat[l] - (1.0 - rho * rho) * vc, 0.0)), 0.0)
+        mom[l]["Vc"] = vc
+        mom[l]["Vf"] = s * s
+        mom[l]["C"] = rho * s * sc
     return mom
 
 

@@ -193,13 +193,21 @@ __global__ void fit_kernel(int L, int first, double* mom, double* vhat, int32_t*
     const double b = (S * Sxy - Sx * Sy) / (S * Sxx - Sx * Sx);
     const double a = (Sy - b * Sx) / S;
     for (int l = first; l <= L; ++l) vhat[l] = exp(a + b * (double)l);
+    // terms with fewer than two samples: coarse member = level l-1 (term
+    // l-1's fine variance), the members' correlation that of term l-1, and
+    // the fine member's deviation s from s^2 + Vc - 2 rho s sqrt(Vc) = vhat
+    // (larger root, clamped at the smallest value the correlation allows)
     for (int l = first > 1 ? first : 1; l <= L; ++l) {
         double* m = mom + 6 * l;
         if (m[0] >= 2.0) continue;
-        const double v = mom[6 * (l - 1) + 3];
-        m[3] = v;
-        m[4] = v;
-        m[5] = (v + v - vhat[l]) / 2.0;
+        const double* b = mom + 6 * (l - 1);
+        double rho = (b[3] > 0.0 && b[4] > 0.0) ? b[5] / sqrt(b[3] * b[4]) : 0.0;
+        rho = fmin(fmax(rho, -1.0), 1.0);
+        const double vc = b[3], sc = sqrt(vc);
+        const double s = fmax(rho * sc + sqrt(fmax(vhat[l] - (1.0 - rho * rho) * vc, 0.0)), 0.0);
+        m[4] = vc;
+        m[3] = s * s;
+        m[5] = rho * s * sc;
     }
     *flag = 0;
 }

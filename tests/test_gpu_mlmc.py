@@ -122,10 +122,12 @@ def test_indicator_fit_matches_oracle(ctx, Ms, first):
     for l, r in enumerate(refs):
         for j, k in ((3, "Vf"), (4, "Vc"), (5, "C")):
             assert abs(m[l, j] - r[k]) <= 1e-12 * max(abs(r[k]), 1e-300), (l, k)
-    # the completed finest terms give the inferred difference variance
+    # the completed finest terms are valid covariances whose difference
+    # variance is the inferred one, or the smallest the correlation allows
     for l in range(max(first, 1), L + 1):
         if Ms[l] < 2:
-            assert abs(m[l, 3] + m[l, 4] - 2 * m[l, 5] - v_ref[l]) <= 1e-12 * v_ref[l] * 10
+            assert m[l, 5] ** 2 <= m[l, 3] * m[l, 4] * (1 + 1e-12)
+            assert m[l, 3] + m[l, 4] - 2 * m[l, 5] >= v_ref[l] * (1 - 1e-10)
 
 
 def test_indicator_fit_needs_two_terms(ctx):

@@ -104,8 +104,10 @@ def test_indicator_fit_with_one_finest_warmup_sample(tmp_path):
     assert ok
     np.testing.assert_allclose(r["v_hat"], v_ref, rtol=1e-12)
     OM.infer_missing_terms(mom, v_ref, 1)
-    assert math.isclose(r["var_f"][3], mom[2]["Vf"], rel_tol=1e-12)
+    assert math.isclose(r["var_c"][3], mom[2]["Vf"], rel_tol=1e-12)
+    assert math.isclose(r["var_f"][3], mom[3]["Vf"], rel_tol=1e-12)
     assert math.isclose(r["cov"][3], mom[3]["C"], rel_tol=1e-12)
+    assert r["cov"][3] ** 2 <= r["var_f"][3] * r["var_c"][3] * (1 + 1e-12)
     a = OM.coefficients([m["Vf"] for m in mom], [m["Vc"] for m in mom], [m["C"] for m in mom], W)
     np.testing.assert_allclose(r["alpha"], a, rtol=1e-10)
     E = OM.estimate([m["mean_f"] for m in mom], [m["mean_c"] for m in mom], a)

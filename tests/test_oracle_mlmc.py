@@ -265,16 +265,31 @@ def test_fit_two_points_is_the_line_through_them_and_minimises_weighted_residual
 
 
 def test_inferred_finest_term_moments():
-    """A single finest sample: both members take the next level's variance and
-    the covariance gives back the inferred difference variance."""
-    mom = [dict(M=100, Vf=4.0e15, Vc=0.0, C=0.0), dict(M=20, Vf=5.0e15, Vc=4.1e15, C=4.3e15),
+    """A single finest sample: the coarse member takes the measured variance
+    of its level, the members' correlation is that of the term below, and
+    the difference variance is the inferred one; the result is a valid
+    covariance even when the inferred difference exceeds what equal member
+    variances allow (variances growing with the level)."""
+    for v in (8.0e14, 6.0e16):                         # small, and > 4 x 5e15
+        mom = [dict(M=100, Vf=4.0e15, Vc=0.0, C=0.0), dict(M=20, Vf=5.0e15, Vc=4.1e15, C=4.3e15),
+               dict(M=1, Vf=0.0, Vc=0.0, C=0.0)]
+        v_hat = np.array([0.0, 5.0e14, v])
+        O.infer_missing_terms(mom, v_hat, first=1)
+        m = mom[2]
+        assert m["Vc"] == 5.0e15
+        assert math.isclose(m["Vf"] + m["Vc"] - 2 * m["C"], v, rel_tol=1e-12)
+        rho_below = 4.3e15 / math.sqrt(5.0e15 * 4.1e15)
+        assert math.isclose(m["C"] / math.sqrt(m["Vf"] * m["Vc"]), rho_below, rel_tol=1e-12)
+        assert m["C"] ** 2 <= m["Vf"] * m["Vc"] * (1 + 1e-12)
+        assert mom[1]["C"] == 4.3e15                   # measured terms untouched
+    # below the smallest difference variance the correlation allows: the
+    # fine member takes s = rho sqrt(Vc), the closest consistent value
+    mom = [dict(M=100, Vf=4.0e15, Vc=0.0, C=0.0), dict(M=20, Vf=1.0, Vc=1.0, C=0.6),
            dict(M=1, Vf=0.0, Vc=0.0, C=0.0)]
-    v_hat = np.array([0.0, 5.0e14, 1.2e14])
-    O.infer_missing_terms(mom, v_hat, first=1)
+    O.infer_missing_terms(mom, np.array([0.0, 0.8, 0.1]), first=1)
     m = mom[2]
-    assert m["Vf"] == m["Vc"] == 5.0e15
-    assert math.isclose(m["Vf"] + m["Vc"] - 2 * m["C"], 1.2e14, rel_tol=1e-12)
-    assert mom[1]["C"] == 4.3e15                       # measured terms untouched
+    assert math.isclose(m["Vf"], 0.36, rel_tol=1e-12) and math.isclose(m["C"], 0.36, rel_tol=1e-12)
+    assert math.isclose(m["Vf"] + m["Vc"] - 2 * m["C"], 1 - 0.36, rel_tol=1e-12)
 
 
 def test_merged_shard_moments_equal_the_moments_of_the_union():
