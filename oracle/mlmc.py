@@ -206,9 +206,12 @@ def infer_missing_terms(mom: list, v_hat, first: int = 1):
     (Vc = its Vf); the correlation of the members is taken from term l-1
     (rho = C / sqrt(Vf Vc) there, 0 if undefined); the fine member's
     standard deviation s then solves s^2 + Vc - 2 rho s sqrt(Vc) = v_hat
-    (V[a - b] = Va + Vb - 2 Cov), the larger root, so that the completed
-    moments are a valid covariance whose difference variance is v_hat
-    (when v_hat < (1 - rho^2) Vc, the smallest such value, s = rho sqrt(Vc)).
+    (V[a - b] = Va + Vb - 2 Cov), the larger root s >= 0, so that the
+    completed moments are a valid covariance whose difference variance is
+    v_hat.  Where v_hat is below the smallest difference variance that
+    correlation allows, s takes its minimiser max(rho sqrt(Vc), 0): the
+    completed difference variance is then (1 - rho^2) Vc for rho >= 0 and Vc
+    (s = 0, no covariance) for rho < 0.
     mom: list of term_moments dicts, updated in place."""
     for l in range(max(first, 1), len(mom)):
         if mom[l]["M"] >= 2:

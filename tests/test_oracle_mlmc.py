@@ -292,6 +292,31 @@ def test_inferred_finest_term_moments():
     assert math.isclose(m["Vf"] + m["Vc"] - 2 * m["C"], 1 - 0.36, rel_tol=1e-12)
 
 
+def test_inferred_term_with_negative_correlation_below():
+    """Completion when the term below has a negative correlation (rho < 0):
+    the difference variance s^2 + Vc - 2 rho s sqrt(Vc) grows with s >= 0, so
+    the smallest value it can take is Vc (s = 0), not (1 - rho^2) Vc.  Checked
+    by brute force over a grid of s: the completed difference variance is
+    max(v_hat, min_s D(s)), and the completed moments are a covariance with
+    correlation rho wherever s > 0."""
+    rho = -0.6
+    for v in (0.1, 0.9, 3.0, 40.0):
+        mom = [dict(M=100, Vf=4.0, Vc=0.0, C=0.0), dict(M=20, Vf=1.0, Vc=1.0, C=rho),
+               dict(M=1, Vf=0.0, Vc=0.0, C=0.0)]
+        O.infer_missing_terms(mom, np.array([0.0, 0.8, v]), first=1)
+        m = mom[2]
+        assert m["Vc"] == 1.0
+        s_grid = np.linspace(0.0, 10.0, 200001)
+        D = s_grid ** 2 + 1.0 - 2.0 * rho * s_grid
+        diff = m["Vf"] + m["Vc"] - 2 * m["C"]
+        assert math.isclose(diff, max(v, D.min()), rel_tol=1e-9), (v, diff)
+        assert m["Vf"] >= 0 and m["C"] ** 2 <= m["Vf"] * m["Vc"] * (1 + 1e-12)
+        if m["Vf"] > 0:
+            assert math.isclose(m["C"] / math.sqrt(m["Vf"] * m["Vc"]), rho, rel_tol=1e-12)
+        else:
+            assert m["C"] == 0.0 and v < 1.0
+
+
 def test_merged_shard_moments_equal_the_moments_of_the_union():
     """The pairwise update gives the two-pass moments of the concatenated
     samples (to round-off), whatever the split, including empty and

@@ -78,3 +78,41 @@ def test_param_count_and_flatten_round_trip():
     q = N.unflatten(f)
     for k in p:
         assert np.array_equal(q[k], p[k])
+
+
+def test_adam_recursion_over_several_steps_closed_forms():
+    """Adam beyond its first step, against closed forms of its moment
+    recursions (geometric series), eps = 0:
+      * constant gradient g: m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2, so
+        the bias-corrected step is lr sign(g) at every t;
+      * alternating gradient g_t = (-1)^(t+1) g:
+        m_t = (1 - b1) g (-1)^(t+1) (1 - (-b1)^t) / (1 + b1), v_t = (1 - b2^t) g^2,
+        so step t moves w by -lr (-1)^(t+1) sign(g) c_t with
+        c_t = (1 - b1)(1 - (-b1)^t) / ((1 + b1)(1 - b1^t)) (v_hat = g^2).
+    A bias correction with a shifted exponent (b^(t+1)) or a step counter
+    that does not advance changes c_t from the second step on."""
+    b1, b2, lr = 0.9, 0.999, 0.01
+    g0 = np.array([0.3, -1e-3, 5.0])
+    # constant gradient
+    p = {"w": np.array([1.0, -2.0, 0.5])}
+    m, v = {"w": np.zeros(3)}, {"w": np.zeros(3)}
+    for t in range(1, 8):
+        N.adam_step(p, {"w": g0.copy()}, m, v, t, lr=lr, b1=b1, b2=b2, eps=0.0)
+        np.testing.assert_allclose(m["w"], (1 - b1 ** t) * g0, rtol=1e-13)
+        np.testing.assert_allclose(v["w"], (1 - b2 ** t) * g0 ** 2, rtol=1e-13)
+        np.testing.assert_allclose(p["w"], np.array([1.0, -2.0, 0.5]) - t * lr * np.sign(g0), rtol=1e-13)
+    # alternating gradient
+    w0 = np.array([1.0, -2.0, 0.5])
+    p = {"w": w0.copy()}
+    m, v = {"w": np.zeros(3)}, {"w": np.zeros(3)}
+    expect = w0.copy()
+    for t in range(1, 8):
+        s = (-1.0) ** (t + 1)
+        N.adam_step(p, {"w": s * g0}, m, v, t, lr=lr, b1=b1, b2=b2, eps=0.0)
+        np.testing.assert_allclose(m["w"], (1 - b1) * g0 * s * (1 - (-b1) ** t) / (1 + b1), rtol=1e-13)
+        np.testing.assert_allclose(v["w"], (1 - b2 ** t) * g0 ** 2, rtol=1e-13)
+        c_t = (1 - b1) * (1 - (-b1) ** t) / ((1 + b1) * (1 - b1 ** t))
+        expect = expect - lr * s * np.sign(g0) * c_t
+        np.testing.assert_allclose(p["w"], expect, rtol=1e-13)
+    # the second step of the alternating sequence is not a signed lr step
+    assert abs((1 - b1) * (1 - b1 ** 2) / ((1 + b1) * (1 - b1 ** 2)) - 1) > 0.5

@@ -513,18 +513,37 @@ def test_conservation_periodic(ndim):
 
 @pytest.mark.parametrize("ndim", [1, 2])
 def test_interface_pressure_velocity_equilibrium(ndim):
-    """Uniform p and u across water/air jumps stay uniform (Johnsen-Colonius
-    adaptation of HLLC, Sec. 2.2)."""
+    """Uniform p and u across jumps of a2 between 0 and 1 stay uniform to
+    round-off (Johnsen-Colonius adaptation of HLLC, Sec. 2.2; Abgrall's
+    criterion).
+
+    Two materials with different gamma (6.12 and 1.4), a 1000:1 density jump
+    and no stiffness (pc1 = 0): p and u stay uniform to 1e-12 relative after
+    40 steps.  With water's stiffness (pc1 = 3.43e8) the oracle recovers p
+    from the stored E, which is dominated by Pi ~ 4e8 against Gamma p ~ 2e4,
+    so the round-off of E (not the scheme) sets the pressure's error: it is
+    held to 1e-12 of the energy's pressure scale max(E) / Gamma_water, and
+    the velocity to 1e-10 relative."""
     n = 32
-    c = cfg_nd(ndim, n, bc="periodic")
     W0 = interface_primitives(ndim, n, seed=11)
+    # no stiffness: round-off of p itself
+    c = cfg_nd(ndim, n, bc="periodic", eos=dict(EOS, pc1=0.0))
+    U, _ = F.run_steps(c, F.prim_to_cons(c, W0), 40)
+    W = F.cons_to_prim(c, U)
+    assert np.abs(W[2 + ndim] / 1.0e5 - 1).max() <= 1e-12
+    for m in range(ndim):
+        assert np.abs(W[2 + m] / W0[2 + m][0, 0, 0] - 1).max() <= 1e-12
+    # stiffened water: round-off of the stored energy
+    c = cfg_nd(ndim, n, bc="periodic")
     U = F.prim_to_cons(c, W0)
+    e_scale = np.abs(U[2 + ndim]).max() * (EOS["gamma1"] - 1.0)
     U, _ = F.run_steps(c, U, 40)
     W = F.cons_to_prim(c, U)
-    p = W[2 + ndim]
-    assert np.abs(p / 1.0e5 - 1).max() < 1e-8
+    assert np.abs(W[2 + ndim] - 1.0e5).max() <= 1e-12 * e_scale
     for m in range(ndim):
-        assert np.abs(W[2 + m] - W0[2 + m][0, 0, 0]).max() < 1e-8 * 35.0
+        assert np.abs(W[2 + m] / W0[2 + m][0, 0, 0] - 1).max() <= 1e-10
+    # the material jump is still there (the test is not of a smeared field)
+    assert W[3 + ndim].min() < 0.5 < W[3 + ndim].max()
 
 
 def test_mirror_symmetry_single_bubble():
