@@ -383,6 +383,14 @@ class OFMLMC:
                     mean_f=m[:, 1].tolist(), mean_c=m[:, 2].tolist(), var_f=m[:, 3].tolist(),
                     var_c=m[:, 4].tolist(), cov=m[:, 5].tolist(), W=list(W), v_hat=v_hat, fit_flag=fit_flag)
 
+    def unfilled_terms(self, res: dict, fit: bool) -> list:
+        """Terms with fewer than two usable samples whose moments the
+        indicator fit did not complete (fit off, or the fit failed: fewer
+        than two qualifying terms; or a term below the fit's first term)."""
+        filled = fit and res.get("fit_flag") == 0
+        first = max(self.fit_first(), 1)
+        return [k for k in range(self.L + 1) if res["M"][k] < 2 and not (filled and k >= first)]
+
     def allocate(self, sig_t2, W, tau: float):
         import torch
         L = self.L
@@ -404,6 +412,9 @@ class OFMLMC:
         terms (App. A.1) until it has two."""
         log = log or self.log
         L = self.L
+        if min_samples < 2 and not fit:
+            raise ValueError("min_samples < 2 needs fit=True: a term's variance needs two samples "
+                             "unless the indicator fit infers it")
         cap = max_samples or [None] * (L + 1)
         if warmup is None:
             W0 = W_model
@@ -422,9 +433,24 @@ class OFMLMC:
             res.update(iteration=it, tau=tau, counts=list(self.count), seconds=time.perf_counter() - t_start,
                        sample_seconds=list(self.time))
             history.append(res)
+            # a term with fewer than two usable samples has no variance of its
+            # own (its moments report 0): unless the indicator fit filled it
+            # in, its error term is unknown, not zero
+            unfilled = self.unfilled_terms(res, fit)
+            if unfilled:
+                res["eps_estimate"] = res["eps"]
+                res["eps"] = math.inf
+                res["unfilled"] = unfilled
             log("iter %d: E=%.6e eps=%.3e tau=%.3e M=%s alpha=%s W=%s" % (
                 it, res["E"], res["eps"], tau, self.count, [round(a, 4) for a in res["alpha"]],
                 ["%.3g" % w for w in W]))
+            if unfilled:
+                target = list(self.count)
+                for k in unfilled:
+                    target[k] = self.count[k] + max(2, min_samples) - res["M"][k]
+                res["next_counts"] = target
+                log("  terms %s have fewer than two usable samples: next counts %s" % (unfilled, target))
+                continue
             if res["eps"] <= tau:
                 break
             M, flag = self.allocate(res["sigma_t2"], W, tau)
@@ -607,6 +633,8 @@ def main(argv=None):
     ap.add_argument("--time-limit", type=float, default=0.0,
                     help="seconds; batches that would end later are not started (exit status 3, resume later)")
     a = ap.parse_args(argv)
+    if a.min_samples < 2 and not a.fit:
+        ap.error("--min-samples below 2 needs --fit (a term's variance needs two samples unless the fit infers it)")
     deadline = time.time() + a.time_limit if a.time_limit > 0 else None
     from workloads.configs import MASTER_SEED, cloud_spec, solver_config, t_end
     os.makedirs(a.dir, exist_ok=True)

@@ -108,9 +108,62 @@ def test_fit_warmup_takes_one_finest_sample(tmp_path, monkeypatch):
 
         def fake_eval(W, classical=False, qoi=None, fit=False, mc=mc):
             seen["fit"] = fit
-            return dict(E=1.0, eps=0.0, alpha=[1.0] * 4, sigma_t2=[0.0] * 4)
+            return dict(E=1.0, eps=0.0, alpha=[1.0] * 4, sigma_t2=[0.0] * 4, M=list(mc.count), fit_flag=0)
 
         monkeypatch.setattr(mc, "evaluate", fake_eval)
         mc.run(rel_tol=0.01, W_model=W_model, fit=fit)
         # W_L / W_l / 2^(L - l): 576/1/8 = 72, 576/9/4 = 16, 576/72/2 = 4, 1
         assert mc.count == [72, 16, 4, last] and seen["fit"] is fit
+
+
+def test_term_without_variance_is_not_converged(tmp_path, monkeypatch):
+    """A term with fewer than two usable samples has no variance (its moments
+    report 0, so its error term would be 0).  Unless the indicator fit filled
+    it in, the loop must not stop on that estimate: the error is unknown and
+    the term gets samples until it has two."""
+    def fake_solve(ctx, specs, bubbles, max_batch_bytes, log, deadline=None, done=None):
+        done(list(range(len(specs))), [fake_qoi(s, b) for s, b in zip(specs, bubbles)], [1.0] * len(specs))
+
+    monkeypatch.setattr(driver, "solve_many", fake_solve)
+    cfg = solver_config("cloud2d", 16)
+    W_model = [1.0, 9.0, 72.0, 576.0]
+    for fit_flag in (driver.capi.OFM_ESINGULAR, 0):
+        mc = driver.OFMLMC(None, cfg, cloud_spec("cloud2d"), [16, 32, 64, 128], "f32", t_end=1e-4,
+                           seed=MASTER_SEED, log=lambda *a: None)
+        calls = []
+
+        def fake_eval(W, classical=False, qoi=None, fit=False, mc=mc, fit_flag=fit_flag):
+            calls.append(list(mc.count))
+            # every term reports a tiny error: only the missing variance can keep the loop going
+            return dict(E=1.0, eps=1e-9, alpha=[1.0] * 4, sigma_t2=[0.0] * 4, M=list(mc.count),
+                        fit_flag=fit_flag)
+
+        monkeypatch.setattr(mc, "evaluate", fake_eval)
+        monkeypatch.setattr(mc, "allocate", lambda *a, **k: pytest.fail("allocated on an unknown error"))
+        out = mc.run(rel_tol=0.01, W_model=W_model, fit=True)
+        if fit_flag == 0:
+            # the fit completed the single finest sample: converged at once
+            assert calls == [[72, 16, 4, 1]] and out["converged"]
+        else:
+            # the fit failed: not converged on one sample; a second finest
+            # sample is asked for, then the estimate stands
+            assert calls == [[72, 16, 4, 1], [72, 16, 4, 2]]
+            assert out["history"][0]["eps"] == float("inf") and out["history"][0]["unfilled"] == [3]
+            assert out["converged"] and mc.count == [72, 16, 4, 2]
+    # without the fit a single sample per term cannot be asked for
+    mc = driver.OFMLMC(None, cfg, cloud_spec("cloud2d"), [16, 32], "f32", t_end=1e-4, seed=MASTER_SEED,
+                       log=lambda *a: None)
+    with pytest.raises(ValueError):
+        mc.run(rel_tol=0.01, W_model=[1.0, 9.0], min_samples=1)
+    with pytest.raises(SystemExit):
+        driver.main(["mlmc2d", "--min-samples", "1", "--dir", str(tmp_path)])
+
+
+def test_failed_samples_count_against_the_two_sample_floor(tmp_path, monkeypatch):
+    """Two solves of which one failed leave one usable sample: still no
+    variance; the term gets another solve."""
+    mc = make(tmp_path, log=lambda *a: None)
+    res = dict(M=[5, 1], fit_flag=None)
+    assert mc.unfilled_terms(res, fit=False) == [1]
+    assert mc.unfilled_terms(dict(M=[5, 1], fit_flag=0), fit=True) == []
+    assert mc.unfilled_terms(dict(M=[1, 3], fit_flag=0), fit=True) == [0]     # below the fit's first term
