@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--cloud", default="cloud500", choices=["cloud500", "cloud50"],
                     help="cloud of the solve (cloud50: 50 bubbles in a ball of 0.25)")
+    ap.add_argument("--weno-order", type=int, default=5, choices=[3, 5],
+                    help="reconstruction of the timed solve (3: the third-order WENO the paper also allows)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 side measurement")
     ap.add_argument("--no-weno3", action="store_true", help="skip the WENO3 side measurement")
     ap.add_argument("--nn", action="store_true",
@@ -246,7 +248,7 @@ def main():
         del x, y
         torch.cuda.empty_cache()
     n = a.n
-    cfg = solver_config(a.cloud, n)
+    cfg = dict(solver_config(a.cloud, n), weno_order=a.weno_order)
     bub = capi.ofm_sample_cloud(cloud_spec(a.cloud), MASTER_SEED, 0, 0)
     ctx = capi.Context(0)
     cells = n ** 3

@@ -164,9 +164,11 @@ __global__ void optimal_M_kernel(int L, const double* sig, const double* W, cons
 // line through ln V[q_l - q_{l-1}] against l over the terms l = first..L
 // with at least two samples, weights (M_l - 1)/2 (Gaussian errors of a
 // sample variance's logarithm).  Terms l >= max(first, 1) with fewer than
-// two samples get their moments from the fit: both members take the
-// variance of level l-1, and the covariance the value that gives the
-// inferred difference variance.  One thread: L is a handful of terms.
+// two samples get their moments from the fit: the coarse member takes the
+// variance of level l-1 (term l-1's fine variance Vc), the members'
+// correlation rho is that of term l-1, and the fine member's deviation s
+// gives the inferred difference variance s^2 + Vc - 2 rho s sqrt(Vc).  One
+// thread: L is a handful of terms.
 __global__ void fit_kernel(int L, int first, double* mom, double* vhat, int32_t* flag)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -195,8 +197,10 @@ __global__ void fit_kernel(int L, int first, double* mom, double* vhat, int32_t*
     for (int l = first; l <= L; ++l) vhat[l] = exp(a + b * (double)l);
     // terms with fewer than two samples: coarse member = level l-1 (term
     // l-1's fine variance), the members' correlation that of term l-1, and
-    // the fine member's deviation s from s^2 + Vc - 2 rho s sqrt(Vc) = vhat
-    // (larger root, clamped at the smallest value the correlation allows)
+    // the fine member's deviation s >= 0 from s^2 + Vc - 2 rho s sqrt(Vc) =
+    // vhat (larger root).  Where vhat is below the smallest difference
+    // variance that correlation allows, s takes the minimiser max(rho
+    // sqrt(Vc), 0): (1 - rho^2) Vc for rho >= 0, Vc (s = 0) for rho < 0.
     for (int l = first > 1 ? first : 1; l <= L; ++l) {
         double* m = mom + 6 * l;
         if (m[0] >= 2.0) continue;

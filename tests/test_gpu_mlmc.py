@@ -149,6 +149,34 @@ def test_indicator_fit_needs_two_terms(ctx):
     assert not ok
 
 
+@pytest.mark.parametrize("C1", [-0.6, 0.6])
+def test_indicator_fit_completion_with_signed_correlation_below(ctx, C1):
+    """The completion of a single-sample finest term when the term below has
+    a negative (or positive) correlation: the device fit and completion
+    equal the oracle's on the same moments (<= 1e-12), for an inferred
+    difference variance above and below the smallest one the correlation
+    allows."""
+    import torch
+    from paper_1705_04374_amd import capi
+    for V2 in (0.05, 30.0):
+        rows = [[100.0, 1.0, 0.0, 4.0, 0.0, 0.0], [50.0, 2.0, 1.0, 1.0, 1.0, C1],
+                [20.0, 3.0, 2.0, 0.5 * V2, 0.5 * V2, 0.25 * V2 * (1 if C1 > 0 else -1)],
+                [1.0, 4.0, 3.0, 0.0, 0.0, 0.0]]
+        mom = torch.tensor(rows, dtype=torch.float64, device="cuda")
+        refs = [dict(M=r[0], mean_f=r[1], mean_c=r[2], Vf=r[3], Vc=r[4], C=r[5]) for r in rows]
+        v_ref, ok = O.fit_indicators([r["M"] for r in refs], [r["Vf"] + r["Vc"] - 2 * r["C"] for r in refs], 1)
+        assert ok
+        O.infer_missing_terms(refs, v_ref, 1)
+        v_hat = torch.full((4,), -1.0, dtype=torch.float64, device="cuda")
+        flag = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+        capi.ofm_ofmlmc_fit_indicators(ctx, 3, 1, mom, v_hat, flag)
+        assert flag.item() == 0
+        np.testing.assert_allclose(v_hat.cpu().numpy(), v_ref, rtol=1e-12, atol=0)
+        m = mom.cpu().numpy()
+        for j, k in ((3, "Vf"), (4, "Vc"), (5, "C")):
+            assert abs(m[3, j] - refs[3][k]) <= 1e-12 * max(abs(refs[3][k]), 1e-300), (V2, k, m[3, j], refs[3][k])
+
+
 def test_merged_shard_moments_match_the_whole(ctx):
     """Per-shard moments merged on the device (the reduction of a per-GPU
     all-reduce) equal the moments of all samples and the oracle's merge."""

@@ -1,6 +1,17 @@
 """GPU parity of the set-network surrogate against the oracle fed the same
 bf16-rounded operands (the oracle accumulates in double, the kernels in float
-on the matrix cores): relative error <= 1e-3 on outputs and gradients."""
+on the matrix cores).
+
+Two bars on outputs and gradients:
+  * whole tensor: relative L2 error <= 1e-3;
+  * element by element: |gpu - ref| <= RTOL |ref| + ATOL max|ref| over the
+    tensor.  The two sides round the same operands to bf16 except where an
+    intermediate activation, accumulated in float on one side and in double
+    on the other, lands on different sides of a bf16 rounding midpoint: that
+    operand then differs by one bf16 ulp (2^-8 relative) and moves the
+    entries it feeds by up to 2^-8 of that one term.  RTOL = 1e-2 and
+    ATOL = 1e-3 bound such flips; the largest element-wise deviations seen
+    are printed."""
 import sys
 
 import numpy as np
@@ -55,6 +66,24 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-30))
 
 
+RTOL, ATOL = 1e-2, 1e-3
+
+
+def elementwise(name, got, ref, rtol=RTOL, atol=ATOL):
+    """Element-wise bar |got - ref| <= rtol |ref| + atol max|ref|; reports the
+    worst entry relative to its own magnitude and to the tensor's scale."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    scale = max(np.abs(ref).max(), 1e-30)
+    d = np.abs(got - ref)
+    bound = rtol * np.abs(ref) + atol * scale
+    worst = np.unravel_index(np.argmax(d / bound), d.shape)
+    say("  %s: max |d|/scale %.2e, max |d|/(rtol|ref| + atol scale) %.3f at %s (ref %.3e, got %.3e), "
+        "entries above 1e-4 of scale: %d of %d" % (name, d.max() / scale, (d / bound).max(), worst, ref[worst],
+                                                   got[worst], int((d > 1e-4 * scale).sum()), d.size))
+    assert np.all(d <= bound), name
+
+
 SIZES = [500, 1, 127, 128, 129, 257, 3, 500, 64]
 
 
@@ -68,6 +97,7 @@ def test_forward_matches_oracle(ctx):
     ref, _ = N.forward(p, x, off, 1.0 / 500, bf16_ops=True)
     got = y.cpu().numpy().astype(np.float64)
     assert rel(got, ref) <= 1e-3, rel(got, ref)
+    elementwise("outputs", got, ref)
     # per set, too (a wrong segment would show here)
     for i in range(len(SIZES)):
         assert rel(got[i], ref[i]) <= 3e-3, (i, rel(got[i], ref[i]))
@@ -89,6 +119,7 @@ def test_gradients_match_oracle(ctx):
     gg = N.unflatten(g.cpu().numpy().astype(np.float64))
     for k in gref:
         assert rel(gg[k], gref[k]) <= 1e-3, (k, rel(gg[k], gref[k]))
+        elementwise(k, gg[k], gref[k])
 
 
 def test_deterministic(ctx):
@@ -104,24 +135,28 @@ def test_deterministic(ctx):
     assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1] == outs[1][1]
 
 
-def test_adam_step_matches_oracle(ctx):
+def test_adam_steps_match_oracle(ctx):
+    """Five training steps: after each, the parameters equal the oracle's
+    Adam (its moment recursions and bias correction pinned over several
+    steps on the CPU) applied to the GPU's gradient at the same parameters
+    (which isolates the update from the gradient's accumulation order)."""
     import torch
     say("nn adam")
     p, x, off, t = problem(4, SIZES)
     net = gpu_net(ctx, p, 1.0 / 500)
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
-    g = torch.zeros(N.param_count(), dtype=torch.float32, device="cuda")
-    net.grads(dev(x), dev(off), dev(t), g, loss)
-    net.train_step(dev(x), dev(off), dev(t), loss)
-    got = torch.zeros(N.param_count(), dtype=torch.float32, device="cuda")
-    net.get_params(got)
-    # the oracle's Adam applied to the GPU's gradient (isolates the update)
     pr = {k: v.copy() for k, v in p.items()}
-    gd = N.unflatten(g.cpu().numpy().astype(np.float64))
     m = {k: np.zeros_like(v) for k, v in p.items()}
     v = {k: np.zeros_like(v) for k, v in p.items()}
-    N.adam_step(pr, gd, m, v, 1)
-    np.testing.assert_allclose(got.cpu().numpy(), N.flatten(pr), rtol=1e-5, atol=1e-7)
+    got = torch.zeros(N.param_count(), dtype=torch.float32, device="cuda")
+    for step in range(1, 6):
+        g = torch.zeros(N.param_count(), dtype=torch.float32, device="cuda")
+        net.grads(dev(x), dev(off), dev(t), g, loss)
+        net.train_step(dev(x), dev(off), dev(t), loss)
+        net.get_params(got)
+        gd = N.unflatten(g.cpu().numpy().astype(np.float64))
+        N.adam_step(pr, gd, m, v, step)
+        np.testing.assert_allclose(got.cpu().numpy(), N.flatten(pr), rtol=1e-5, atol=1e-7, err_msg="step %d" % step)
 
 
 def test_features_match_oracle(ctx):
