@@ -34,6 +34,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace ofm {
 
 // ---------------------------------------------------------------------------
@@ -529,9 +531,15 @@ constexpr int round_up64(int x) { return (x + 63) / 64 * 64; }
 template <int TX, int TY> constexpr int stage_threads() { return round_up64(TX * TY); }
 
 // Occupancy target of the stage kernel: three wavefronts per SIMD for the
-// float kernels (at most 168 VGPRs), one for double (whose LDS tile allows no
-// more).
-template <typename T> constexpr int stage_waves_per_eu() { return sizeof(T) == 4 ? 3 : 1; }
+// float kernels (at most 168 VGPRs), two for double (at most 256 VGPRs; the
+// split x-y pass below keeps a 16 x 8 tile's LDS under a quarter of the CU's).
+template <typename T> constexpr int stage_waves_per_eu() { return sizeof(T) == 4 ? 3 : 2; }
+
+// The x-y part of a plane in one pass (float: the edges of both axes live in
+// LDS at once, then all faces) or split by axis (double: the x edges, x faces
+// and x sums, then the same for y, each axis's face fluxes written over its
+// own edges after a barrier), which needs about half the LDS for the edges.
+template <typename T> constexpr bool stage_split_xy() { return sizeof(T) == 8; }
 
 // RK stage STAGE = 0, 1, 2 (compiled separately: only the last carries the
 // reduction, only the first skips dU); WENO order ORD = 5 or 3.
@@ -559,11 +567,18 @@ stage_kernel(LaunchArgs a)
     constexpr int WSZ = NV * HX * HY;
     constexpr int FSZ = (NV + 1) * FS;
     constexpr int AL = WSZ > FSZ ? WSZ : FSZ;          // W plane and face fluxes share LDS
-    __shared__ T smem[AL + 2 * NV * ES];
-    T* sW = smem;                          // [NV][HY][HX]
-    T* sF = smem;                          // [NV+1][FS]   (after the edges are built)
-    T* sEm = smem + AL;                    // left edges  [NV][ES]
-    T* sEp = sEm + NV * ES;                // right edges [NV][ES]
+    // split pass: edge tasks of one axis at a time; an axis's face fluxes
+    // ((NV+1) x its faces <= 2 NV x its edge tasks) overwrite its edges
+    constexpr bool SPLIT = stage_split_xy<T>();
+    constexpr int ESX = EXN > EYN ? EXN : EYN;
+    constexpr int EST = SPLIT ? ESX : ES;              // stride of the edge arrays
+    static_assert(!SPLIT || ((NV + 1) * FXN <= 2 * NV * ESX && (NV + 1) * FYN <= 2 * NV * ESX), "face alias");
+    static_assert(!SPLIT || (FXN <= 2 * NT && FYN <= 2 * NT), "at most two faces per thread in the split pass");
+    __shared__ T smem[SPLIT ? WSZ + 2 * NV * ESX : AL + 2 * NV * ES];
+    T* sW = smem;                                      // [NV][HY][HX]
+    T* sEm = smem + (SPLIT ? WSZ : AL);                // left edges  [NV][EST]
+    T* sEp = sEm + NV * EST;                           // right edges [NV][EST]
+    T* sF = SPLIT ? sEm : smem;                        // face fluxes [NV+1][faces] (after the edges are read)
 
     const int wi = xcd_swizzle(blockIdx.x, gridDim.x);
     if (wi >= a.n_work) return;
@@ -621,9 +636,86 @@ stage_kernel(LaunchArgs a)
         }
     };
 
+    // split x-y pass, one axis (DIR = 0: x, 1: y): edges of the axis's tasks
+    // into sEm/sEp, then its faces (at most two per thread, fluxes kept in
+    // registers across the barrier that ends the edge reads), written over
+    // the edges, and the cell's flux differences added to xy
+    auto axis_xy = [&](auto dir_c, T (&xy)[NV + 1]) {
+        constexpr int DIR = decltype(dir_c)::value;
+        constexpr int NE = DIR == 0 ? EXN : EYN;
+        constexpr int NF = DIR == 0 ? FXN : FYN;
+        for (int e = tid; e < NE; e += NT) {
+            int base, stride;
+            if (DIR == 0) {
+                const int row = e / (TX + 2), cx = e % (TX + 2) - 1;
+                base = (row + (ND >= 2 ? 3 : 0)) * HX + cx + 1;
+                stride = 1;
+            } else {
+                const int cy = e / TX - 1, col = e % TX;
+                base = (cy + 1) * HX + col + 3;
+                stride = HX;
+            }
+            T st[5][NV], lo[NV], hi[NV];
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) st[k][v] = sW[v * HY * HX + base + k * stride];
+            cell_edges<T, ND, ORD>(ph, st, lo, hi);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) { sEm[v * EST + e] = lo[v]; sEp[v * EST + e] = hi[v]; }
+        }
+        __syncthreads();
+        T fa[NV + 1], fb[NV + 1];
+        auto face = [&](int f, T (&fl)[NV + 1]) {
+            T wl[NV], wr[NV];
+            int l, r;
+            if (DIR == 0) {
+                const int row = f / (TX + 1), i = f % (TX + 1);
+                l = row * (TX + 2) + i;
+                r = l + 1;
+            } else {
+                const int j = f / TX, col = f % TX;
+                l = j * TX + col;
+                r = l + TX;
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v) { wl[v] = sEp[v * EST + l]; wr[v] = sEm[v * EST + r]; }
+            hllc<T, ND, (DIR < ND ? DIR : 0)>(ph, wl, wr, fl);
+        };
+        const bool ha = tid < NF, hb = tid + NT < NF;
+        if (ha) face(tid, fa);
+        if (hb) face(tid + NT, fb);
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v <= NV; ++v) {
+            if (ha) sF[v * NF + tid] = fa[v];
+            if (hb) sF[v * NF + tid + NT] = fb[v];
+        }
+        __syncthreads();
+        if (DIR == 0) {
+            const int fx = ty * (TX + 1) + tx;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) xy[v] = sF[v * NF + fx] - sF[v * NF + fx + 1];
+            xy[NV] = sF[NV * NF + fx + 1] - sF[NV * NF + fx];
+        } else {
+            const int fy = ty * TX + tx;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) xy[v] += sF[v * NF + fy] - sF[v * NF + fy + TX];
+            xy[NV] += sF[NV * NF + fy + TX] - sF[NV * NF + fy];
+        }
+    };
+
     // x-y part of the plane now in sW: per-cell sums of the face-flux
     // differences (F_- - F_+) and of the face-velocity differences (u_+ - u_-)
-    auto plane_xy = [&](T (&xy)[NV + 1]) {
+    auto plane_xy_split = [&](T (&xy)[NV + 1]) {
+        axis_xy(std::integral_constant<int, 0>{}, xy);
+        if constexpr (ND >= 2) {
+            __syncthreads();                 // the x sums are read before the y edges overwrite them
+            axis_xy(std::integral_constant<int, 1>{}, xy);
+        }
+    };
+
+    auto plane_xy_joint = [&](T (&xy)[NV + 1]) {
         // edges along x of cells -1..TX of every row, along y of rows -1..TY
         for (int e = tid; e < ES; e += NT) {
             // stencil of five cells through the centre cell, `stride` apart in sW
@@ -681,6 +773,13 @@ stage_kernel(LaunchArgs a)
             for (int v = 0; v < NV; ++v) xy[v] += sF[v * FS + fy] - sF[v * FS + fy + TX];
             xy[NV] += sF[NV * FS + fy + TX] - sF[NV * FS + fy];
         }
+    };
+
+    auto plane_xy = [&](T (&xy)[NV + 1]) {
+        if constexpr (SPLIT)
+            plane_xy_split(xy);
+        else
+            plane_xy_joint(xy);
     };
 
     // L(U) of one cell from its flux-difference sums and primitives
@@ -771,7 +870,7 @@ stage_kernel(LaunchArgs a)
             if (early && xy_work) load_cell();
             T xy[NV + 1];
             if (xy_work) {
-                __syncthreads();
+                if constexpr (!SPLIT) __syncthreads();   // sW is the joint pass's face-flux area
                 load_plane(p);
                 __syncthreads();
                 plane_xy(xy);
@@ -1089,7 +1188,7 @@ static hipError_t launch_reduce_t(const LaunchArgs& a, hipStream_t s)
 // Tile shapes compiled for each (precision, dimension).
 #define OFM_FOR_TILES(X)                                                               \
     X(float, 3, 16, 14) X(float, 3, 16, 16) X(float, 3, 16, 8)                         \
-    X(double, 3, 16, 8) X(double, 3, 16, 14) X(double, 3, 8, 8)                        \
+    X(double, 3, 16, 8) X(double, 3, 16, 14) X(double, 3, 16, 16)                      \
     X(float, 2, 16, 14) X(float, 2, 16, 16) X(double, 2, 16, 14) X(double, 2, 16, 8)   \
     X(float, 1, 256, 1) X(double, 1, 256, 1) X(float, 1, 64, 1) X(double, 1, 64, 1)
 

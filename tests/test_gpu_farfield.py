@@ -106,7 +106,7 @@ def test_farfield_tiling_invariance_bitwise(ctx):
     say("far field tiling invariance")
     cfg = far("cloud50", 20)
     bub = sample_cloud(cloud_spec("cloud50"), MASTER_SEED, 0, 2)
-    outs = [run(ctx, cfg, "f64", 40, bubbles=bub, tune=t)[0] for t in [(16, 8, 16, 2), (8, 8, 7, 2), (16, 14, 3, 2)]]
+    outs = [run(ctx, cfg, "f64", 40, bubbles=bub, tune=t)[0] for t in [(16, 8, 16, 2), (16, 16, 7, 2), (16, 14, 3, 2)]]
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
     R, _ = OF.run_steps(cfg, OF.init_state(cfg, bub), 40)

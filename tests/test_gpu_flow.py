@@ -102,7 +102,7 @@ def test_fp64_ragged_tiles_and_chunks(ctx):
     cfg = solver_config("cloud50", 20)
     bub = sample_cloud(cloud_spec("cloud50"), MASTER_SEED, 0, 2)
     R, _ = OF.run_steps(cfg, OF.init_state(cfg, bub), 12)
-    for tune in [(16, 8, 16, 2), (8, 8, 7, 2), (16, 14, 32, 2)]:
+    for tune in [(16, 8, 16, 2), (16, 16, 7, 2), (16, 14, 32, 2)]:
         U, _, _ = gpu_run(ctx, cfg, "f64", bubbles=bub, n_steps=12, tune=tune)
         assert np.all(max_rel_field(oracle_shape(cfg, U), R) <= 1e-11), tune
 
@@ -115,7 +115,7 @@ def test_fp64_tiling_invariance_bitwise(ctx):
     cfg = solver_config("cloud50", 32)
     bub = sample_cloud(cloud_spec("cloud50"), MASTER_SEED, 0, 4)
     outs = [gpu_run(ctx, cfg, "f64", bubbles=bub, n_steps=6, tune=t)[0]
-            for t in [(16, 8, 16, 2), (8, 8, 32, 2), (16, 14, 5, 2), (16, 8, 1, 2)]]
+            for t in [(16, 8, 16, 2), (16, 16, 32, 2), (16, 14, 5, 2), (16, 8, 1, 2)]]
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
     again = gpu_run(ctx, cfg, "f64", bubbles=bub, n_steps=6, tune=(16, 8, 16, 2))[0]
