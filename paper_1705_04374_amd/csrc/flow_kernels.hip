@@ -76,6 +76,13 @@ template <> struct Num<double> {
     static constexpr double round_tol = 1e-12;
 };
 
+// Device memory seen as the global address space.  The state arrays come
+// from descriptors in memory, so the compiler cannot infer where they live
+// and would use flat accesses; a flat load also counts against the LDS wait
+// counter, so every LDS wait of the x-y work would wait for the column and
+// cell loads issued ahead of it.
+template <typename T> using glob = __attribute__((address_space(1))) T;
+
 template <typename T> struct Phys {
     T g1inv, dginv, pi1, dpi;
     T eps;             // (12/13) x the WENO epsilon (the indicators' scale in weno5_cell)
@@ -600,9 +607,9 @@ stage_kernel(LaunchArgs a)
     const bool mine = tid < TX * TY && gx < n && (ND < 2 || gy < n);
     const int64_t ncell = ND == 3 ? (int64_t)n * n * n : (ND == 2 ? (int64_t)n * n : (int64_t)n);
     const int64_t plane = ND >= 2 ? (int64_t)n * n : (int64_t)n;
-    const T* __restrict__ ua = (const T*)d.buf[a.src];
-    T* __restrict__ ub = (T*)d.buf[a.src ^ 1];
-    T* __restrict__ du = (T*)d.du;
+    const glob<T>* __restrict__ ua = (const glob<T>*)d.buf[a.src];
+    glob<T>* __restrict__ ub = (glob<T>*)d.buf[a.src ^ 1];
+    glob<T>* __restrict__ du = (glob<T>*)d.du;
     const T dt = (T)st->dt;
     const T ih = (T)(1.0 / d.h);
     constexpr int stage = STAGE;
@@ -927,7 +934,7 @@ __global__ void __launch_bounds__((stage_threads<TX, TY>())) reduce_kernel(Launc
     const int gx = ttx * TX + tx, gy = tty * TY + ty;
     const int64_t ncell = ND == 3 ? (int64_t)n * n * n : (ND == 2 ? (int64_t)n * n : (int64_t)n);
     const int64_t plane = ND >= 2 ? (int64_t)n * n : (int64_t)n;
-    const T* u = (const T*)d.buf[a.src];
+    const glob<T>* u = (const glob<T>*)d.buf[a.src];
     Red red;
     red.init();
     if (ty < TY && gx < n && (ND < 2 || gy < n)) {
@@ -1108,7 +1115,7 @@ __global__ void __launch_bounds__(256) init_kernel(InitArgs a)
     const double G = a.ph.g1inv + a2 * (a.ph.g2inv - a.ph.g1inv);
     const int64_t ncell = ND == 3 ? (int64_t)n * n * n : (ND == 2 ? (int64_t)n * n : (int64_t)n);
     const int64_t idx = ((int64_t)k * (ND >= 2 ? n : 1) + j) * n + i;
-    T* u = (T*)a.u;
+    glob<T>* u = (glob<T>*)a.u;
     constexpr int NV = 4 + ND;
     u[0 * ncell + idx] = (T)((1.0 - a2) * a.rho1);
     u[1 * ncell + idx] = (T)(a2 * a.rho2);
