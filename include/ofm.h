@@ -227,6 +227,27 @@ int ofm_state_to_conserved(ofm_ctx* ctx, const ofm_solve_spec* spec, const ofm_s
 int ofm_step(ofm_ctx* ctx, const ofm_solve_spec* spec, ofm_state_view* st, int64_t n_steps,
              ofm_qoi* qoi, double* dts, void* stream);
 
+/* Size of the fixed device scratch of ofm_step_noalloc, per GPU. */
+#define OFM_NOALLOC_SCRATCH_BYTES (4u << 20)
+
+/* ofm_step for callers that cannot allocate memory (code under graph
+ * capture, tight serving loops, harnesses that forbid device or pinned
+ * allocations): the same kernels and launches, on the caller's stream, with
+ * the same results bit for bit; it calls no hipMalloc, hipHostMalloc or
+ * hipFree and creates no events.  Its scratch (the sample's descriptor and
+ * dynamic state, 64 B of reduction partial and 8 B of work list per tile of
+ * the tuned tiling, and 8 B per step when dts is given) is a fixed device
+ * array of OFM_NOALLOC_SCRATCH_BYTES per GPU, kept until the process ends;
+ * a call that needs more (e.g. a 16 x 16 x 16 tiling of a 1024^3 grid, or a
+ * step log longer than about 500 000 steps) returns OFM_EINVAL before any
+ * launch.  Every call on one GPU shares that array: calls that overlap in
+ * time on one GPU (other streams, other threads) race and must be
+ * serialised by the caller.  Arguments, results and u/u_tmp exchange as for
+ * ofm_step; per-launch kernel timing (ofm_kernel_timing) does not apply.
+ * Synchronises the stream (the QoI is returned in host memory). */
+int ofm_step_noalloc(ofm_ctx* ctx, const ofm_solve_spec* spec, ofm_state_view* st, int64_t n_steps,
+                     ofm_qoi* qoi, double* dts, void* stream);
+
 /* ---- solves -------------------------------------------------------------- */
 
 /* Solve one sample to spec->t_end (or spec->n_steps steps) and return its QoI

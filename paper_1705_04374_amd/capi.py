@@ -20,12 +20,13 @@ OFM_OK, OFM_EINVAL, OFM_ENOMEM, OFM_EHIP, OFM_EUNSUPPORTED, OFM_ESINGULAR, OFM_E
 OFM_F32, OFM_F64 = 0, 1
 OFM_BC_ZERO_GRADIENT, OFM_BC_PERIODIC, OFM_BC_CHARACTERISTIC = 0, 1, 2
 OFM_MODE_TOLERANCE, OFM_MODE_BUDGET = 0, 1
+OFM_NOALLOC_SCRATCH_BYTES = 4 << 20     # fixed device scratch of ofm_step_noalloc, per GPU
 SAMPLE_OK, SAMPLE_NONFINITE, SAMPLE_NEGATIVE_C2, SAMPLE_MAX_STEPS = 0, 1, 2, 3
 
 # Every symbol include/ofm.h declares.
 EXPORTS = [
     "ofm_ctx_create", "ofm_ctx_destroy", "ofm_last_error", "ofm_sample_cloud", "ofm_state_init",
-    "ofm_state_from_primitive", "ofm_state_to_conserved", "ofm_step", "ofm_solve", "ofm_solve_batch", "ofm_run_begin", "ofm_run_advance", "ofm_run_status", "ofm_run_destroy",
+    "ofm_state_from_primitive", "ofm_state_to_conserved", "ofm_step", "ofm_step_noalloc", "ofm_solve", "ofm_solve_batch", "ofm_run_begin", "ofm_run_advance", "ofm_run_status", "ofm_run_destroy",
     "ofm_last_solve_stats",
     "ofm_mlmc_moments", "ofm_ofmlmc_coefficients", "ofm_ofmlmc_errors", "ofm_ofmlmc_estimate",
     "ofm_ofmlmc_optimal_M", "ofm_ofmlmc_fit_indicators", "ofm_mlmc_merge_moments", "ofm_tune_set", "ofm_tune_get", "ofm_autotune", "ofm_kernel_timing", "ofm_kernel_times",
@@ -124,6 +125,7 @@ def lib():
         L.ofm_state_from_primitive.argtypes = [vp, C.POINTER(SolveSpec), vp, C.POINTER(StateView), vp]
         L.ofm_state_to_conserved.argtypes = [vp, C.POINTER(SolveSpec), C.POINTER(StateView), vp, vp]
         L.ofm_step.argtypes = [vp, C.POINTER(SolveSpec), C.POINTER(StateView), i64, C.POINTER(Qoi), dp, vp]
+        L.ofm_step_noalloc.argtypes = [vp, C.POINTER(SolveSpec), C.POINTER(StateView), i64, C.POINTER(Qoi), dp, vp]
         L.ofm_solve.argtypes = [vp, C.POINTER(SolveSpec), dp, i32, C.POINTER(Qoi), vp]
         L.ofm_solve_batch.argtypes = [vp, C.POINTER(BatchItem), i32, C.POINTER(Qoi), vp]
         L.ofm_last_solve_stats.argtypes = [vp, dp, dp, dp]
@@ -280,6 +282,14 @@ def ofm_step(ctx: Context, spec: SolveSpec, st: StateView, n_steps: int, stream=
     ctx.check(lib().ofm_step(ctx.h, C.byref(spec), C.byref(st), n_steps, C.byref(q),
                              dts.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)))
     return q.as_dict(), dts[:n_steps]
+
+
+def ofm_step_noalloc(ctx: Context, spec: SolveSpec, st: StateView, n_steps: int, stream=None, log_dts=True):
+    q = Qoi()
+    dts = np.zeros(max(n_steps, 1))
+    ptr = dts.ctypes.data_as(C.POINTER(C.c_double)) if log_dts else None
+    ctx.check(lib().ofm_step_noalloc(ctx.h, C.byref(spec), C.byref(st), n_steps, C.byref(q), ptr, _stream(stream)))
+    return q.as_dict(), (dts[:n_steps] if log_dts else None)
 
 
 def ofm_solve(ctx: Context, spec: SolveSpec, bubbles, stream=None) -> dict:

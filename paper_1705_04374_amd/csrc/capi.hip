@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -126,6 +127,38 @@ static size_t state_bytes(const ofm_solve_spec& s)
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Descriptor of one sample of a launch: its arrays, tiling (its tiles are
+// tile0 .. tile0 + ntiles - 1 of the launch's partials), step control and the
+// sensors' balls.
+static SampleDesc make_desc(const ofm_solve_spec& s, const TileChoice& tc, int tile0, void* b0, void* b1, void* du)
+{
+    SampleDesc d{};
+    const int nd = s.ndim;
+    d.buf[0] = b0;
+    d.buf[1] = b1;
+    d.du = du;
+    d.n = s.n;
+    d.ntx = (s.n + tc.tx - 1) / tc.tx;
+    d.nty = nd >= 2 ? (s.n + tc.ty - 1) / tc.ty : 1;
+    d.nzc = nd == 3 ? (s.n + tc.zchunk - 1) / tc.zchunk : 1;
+    d.tile0 = tile0;
+    d.ntiles = d.ntx * d.nty * d.nzc;
+    d.h = 1.0 / (double)s.n;
+    d.cfl = s.cfl;
+    d.t_end = s.n_steps > 0 ? INFINITY : s.t_end;
+    d.n_steps = s.n_steps;
+    d.max_steps = s.max_steps;
+    // sensors (ofm_qoi): pressure ball of radius max(R_c / 40, 1.01 half
+    // cell diagonals), gas-fraction ball of radius R_c, at the cloud centre
+    for (int a = 0; a < 3; ++a) d.centre[a] = s.center[a];
+    double rp = s.cloud_radius / 40.0;
+    const double hd = 1.01 * 0.5 * d.h * sqrt((double)s.ndim);
+    if (hd > rp) rp = hd;
+    d.r2_p = rp * rp;
+    d.r2_a = s.cloud_radius * s.cloud_radius;
+    return d;
+}
 
 // One batched run: all members share ndim/precision/bc/eos.
 struct Member {
@@ -279,33 +312,8 @@ static int run_begin(ofm_ctx* ctx, ofm_run& r, bool init, int64_t dts_len, hipSt
     r.desc.assign(ns, SampleDesc{});
     int tiles = 0;
     for (int i = 0; i < ns; ++i) {
-        SampleDesc& d = r.desc[i];
-        const ofm_solve_spec& s = mem[i].spec;
-        d.buf[0] = mem[i].buf0;
-        d.buf[1] = mem[i].buf1;
-        d.du = mem[i].du;
-        d.n = s.n;
-        d.ntx = (s.n + tc.tx - 1) / tc.tx;
-        d.nty = nd >= 2 ? (s.n + tc.ty - 1) / tc.ty : 1;
-        d.nzc = nd == 3 ? (s.n + tc.zchunk - 1) / tc.zchunk : 1;
-        d.tile0 = tiles;
-        d.ntiles = d.ntx * d.nty * d.nzc;
-        d.h = 1.0 / (double)s.n;
-        d.cfl = s.cfl;
-        d.t_end = s.n_steps > 0 ? INFINITY : s.t_end;
-        d.n_steps = s.n_steps;
-        d.max_steps = s.max_steps;
-        // sensors (ofm_qoi): pressure ball of radius max(R_c / 40, 1.01 half
-        // cell diagonals), gas-fraction ball of radius R_c, at the cloud centre
-        for (int a = 0; a < 3; ++a) d.centre[a] = s.center[a];
-        {
-            double rp = s.cloud_radius / 40.0;
-            const double hd = 1.01 * 0.5 * d.h * sqrt((double)s.ndim);
-            if (hd > rp) rp = hd;
-            d.r2_p = rp * rp;
-            d.r2_a = s.cloud_radius * s.cloud_radius;
-        }
-        tiles += d.ntiles;
+        r.desc[i] = make_desc(mem[i].spec, tc, tiles, mem[i].buf0, mem[i].buf1, mem[i].du);
+        tiles += r.desc[i].ntiles;
     }
     // work list: larger samples first, tiles of a sample contiguous
     r.order.resize(ns);
@@ -554,6 +562,60 @@ static void to_qoi(const ofm_solve_spec& s, const SampleState& st, ofm_qoi* q)
 
 }  // namespace ofm
 
+// ---------------------------------------------------------------------------
+// Stepping without allocation (ofm_step_noalloc)
+// ---------------------------------------------------------------------------
+// The stepper's scratch lives in a fixed device array: the sample
+// descriptor, its dynamic state, one reduction partial per tile, the work
+// list and the step-size log.  Every GPU the library runs on holds its own
+// copy until the process ends; all calls on that GPU share it.
+static __device__ __align__(256) unsigned char scratch[OFM_NOALLOC_SCRATCH_BYTES];
+
+namespace ofm {
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static char* g_scratch[kMaxDevices] = {};   // device address of `scratch`, per device
+
+// Resolve the device address of `scratch` on ctx's device (current), once
+// per device.  Host code uses only this address: the array's name is a
+// host-side stand-in.
+static int resolve_scratch(ofm_ctx* ctx)
+{
+    if (ctx->device >= kMaxDevices) return fail(ctx, OFM_EUNSUPPORTED, "device %d beyond %d", ctx->device, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[ctx->device]) return OFM_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(ctx, OFM_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch[ctx->device] = (char*)p;
+    return OFM_OK;
+}
+
+static char* scratch_of(const ofm_ctx* ctx)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return ctx->device < kMaxDevices ? g_scratch[ctx->device] : nullptr;
+}
+
+// Descriptor, a zeroed dynamic state and the work list (tiles 0..ntiles-1
+// of sample 0), written by the device from kernel arguments (no copies from
+// host memory).
+__global__ void __launch_bounds__(256) noalloc_setup_kernel(SampleDesc d, SampleDesc* dd, SampleState* ds,
+                                                            WorkItem* work, int ntiles)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i == 0) {
+        *dd = d;
+        SampleState z{};
+        *ds = z;
+    }
+    if (i < ntiles) work[i] = WorkItem{ 0, i };
+}
+
+}  // namespace ofm
+
 using namespace ofm;
 
 extern "C" {
@@ -571,6 +633,13 @@ int ofm_ctx_create(int device, ofm_ctx** out)
     if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
         delete c;
         return fail(nullptr, OFM_EHIP, "ofm_ctx_create: stream creation failed");
+    }
+    const int rc = resolve_scratch(c);
+    if (rc) {
+        const std::string msg = c->err;
+        (void)hipStreamDestroy(c->stream);
+        delete c;
+        return fail(nullptr, rc, "ofm_ctx_create: %s", msg.c_str());
     }
     *out = c;
     return OFM_OK;
@@ -673,6 +742,72 @@ int ofm_step(ofm_ctx* ctx, const ofm_solve_spec* spec, ofm_state_view* st, int64
     if (rc) return rc;
     to_qoi(mem[0].spec, out[0], qoi);
     if (out[0].steps & 1) std::swap(st->u, st->u_tmp);
+    return OFM_OK;
+}
+
+int ofm_step_noalloc(ofm_ctx* ctx, const ofm_solve_spec* spec, ofm_state_view* st, int64_t n_steps, ofm_qoi* qoi,
+                     double* dts, void* stream)
+{
+    if (!ctx) return fail(nullptr, OFM_EINVAL, "null context");
+    int rc = validate(ctx, spec);
+    if (rc) return rc;
+    if (!st || !st->u || !st->u_tmp || !st->du || n_steps < 1 || !qoi)
+        return fail(ctx, OFM_EINVAL, "ofm_step_noalloc: bad arguments");
+    ofm_solve_spec s = *spec;
+    s.n_steps = n_steps;
+    s.max_steps = n_steps;
+    const TileChoice tc = ctx->tuning.choose(s.precision, s.ndim, s.n, 1);
+    const SampleDesc d = make_desc(s, tc, 0, st->u, st->u_tmp, st->du);
+    // scratch layout: descriptor | state | partials | work list | step sizes
+    const size_t o_state = align256(sizeof(SampleDesc));
+    const size_t o_part = align256(o_state + sizeof(SampleState));
+    const size_t o_work = align256(o_part + sizeof(TilePartial) * (size_t)d.ntiles);
+    const size_t o_dt = align256(o_work + sizeof(WorkItem) * (size_t)d.ntiles);
+    const size_t need = o_dt + (dts ? sizeof(double) * (size_t)n_steps : 0);
+    if (need > (size_t)OFM_NOALLOC_SCRATCH_BYTES)
+        return fail(ctx, OFM_EINVAL,
+                    "ofm_step_noalloc: %d tiles%s need %zu bytes of scratch; the fixed scratch holds %zu",
+                    d.ntiles, dts ? " and the step-size log" : "", need, (size_t)OFM_NOALLOC_SCRATCH_BYTES);
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    char* base = scratch_of(ctx);
+    if (!base) return fail(ctx, OFM_EHIP, "ofm_step_noalloc: scratch of device %d not resolved", ctx->device);
+    SampleDesc* d_desc = (SampleDesc*)base;
+    SampleState* d_state = (SampleState*)(base + o_state);
+    TilePartial* d_part = (TilePartial*)(base + o_part);
+    WorkItem* d_work = (WorkItem*)(base + o_work);
+    double* d_dt = dts ? (double*)(base + o_dt) : nullptr;
+    const int64_t dt_len = dts ? n_steps : 0;
+    hipStream_t hs = (hipStream_t)stream;
+    hipLaunchKernelGGL(noalloc_setup_kernel, dim3((d.ntiles + 255) / 256), dim3(256), 0, hs, d, d_desc, d_state,
+                       d_work, d.ntiles);
+    HIPCHK(ctx, hipGetLastError());
+    LaunchArgs la{};
+    la.ph = make_phys(s);
+    la.work = d_work;
+    la.n_work = d.ntiles;
+    la.zchunk = tc.zchunk;
+    la.desc = d_desc;
+    la.state = d_state;
+    la.part = d_part;
+    la.bc = s.bc;
+    la.src = 0;
+    // the same launches as ofm_step: the reduction of the initial level, then
+    // per step three stages (stage k of step g reads buffer (g + k) & 1) and
+    // the finalisation
+    HIPCHK(ctx, launch_reduce(s.precision, s.ndim, tc.tx, tc.ty, la, hs));
+    HIPCHK(ctx, launch_finalize(d_desc, d_state, d_part, 1, 1, d_dt, dt_len, hs));
+    for (int64_t g = 0; g < n_steps; ++g)
+        for (int stg = 0; stg < 3; ++stg) {
+            la.src = (int)((g + stg) & 1);
+            HIPCHK(ctx, launch_stage(s.precision, s.ndim, tc.tx, tc.ty, la, stg, hs));
+            if (stg == 2) HIPCHK(ctx, launch_finalize(d_desc, d_state, d_part, 1, 0, d_dt, dt_len, hs));
+        }
+    SampleState out;
+    HIPCHK(ctx, hipMemcpyAsync(&out, d_state, sizeof out, hipMemcpyDeviceToHost, hs));
+    if (dts) HIPCHK(ctx, hipMemcpyAsync(dts, d_dt, sizeof(double) * (size_t)n_steps, hipMemcpyDeviceToHost, hs));
+    HIPCHK(ctx, hipStreamSynchronize(hs));
+    to_qoi(s, out, qoi);
+    if (out.steps & 1) std::swap(st->u, st->u_tmp);
     return OFM_OK;
 }
 
