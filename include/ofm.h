@@ -317,7 +317,8 @@ typedef struct ofm_tune_result {
 int ofm_tune_get(const ofm_ctx* ctx, int32_t precision, int32_t ndim, int32_t n, ofm_tune_result* out);
 
 /* Measure every compiled tile shape (and, in 3-D, z-chunks of 8, 16, 32 and
- * 64 planes not larger than n) of the stage kernel for spec's precision,
+ * 64 planes not larger than n, and those whose workgroup count fills 1 to 8
+ * whole rounds of the device's CUs at the tile's occupancy) of the stage kernel for spec's precision,
  * dimension and grid, by stepping the caller's state st [dev] `steps` time
  * steps per candidate with per-launch events, and store the fastest as the
  * entry ofm_tune_set would write; out [host] receives it.  The state is

@@ -972,14 +972,29 @@ int ofm_autotune(ofm_ctx* ctx, const ofm_solve_spec* spec, ofm_state_view* st, i
         return fail(ctx, OFM_EINVAL, "ofm_autotune: bad arguments");
     int tiles[32][2];
     const int nt = std::min(tile_list(spec->precision, spec->ndim, tiles, 32), 32);
-    std::vector<int> zcs;
-    if (spec->ndim == 3) {
-        for (int z : { 8, 16, 32, 64 })
-            if (z <= spec->n) zcs.push_back(z);
-        if (zcs.empty()) zcs.push_back(spec->n);
-    } else {
-        zcs.push_back(1);
-    }
+    int cus = 0;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) cus = 0;
+    // z-chunks of a tile: fixed sizes, and those whose workgroup count fills
+    // whole rounds of the GPU (every CU holding its resident workgroups; a
+    // last round partly empty leaves CUs idle while it runs)
+    auto zchunks = [&](int tx, int ty) {
+        std::vector<int> z;
+        if (spec->ndim != 3) return std::vector<int>{ 1 };
+        for (int c : { 8, 16, 32, 64 })
+            if (c <= spec->n) z.push_back(c);
+        const int per = stage_blocks_per_cu(spec->precision, spec->ndim, tx, ty, spec->weno_order == 3 ? 3 : 5);
+        const long long slots = (long long)cus * per;
+        const long long xy = (long long)((spec->n + tx - 1) / tx) * ((spec->n + ty - 1) / ty);
+        for (int r = 1; slots > 0 && r <= 8; ++r) {
+            const long long nzc = (r * slots + xy - 1) / xy;
+            if (nzc > spec->n) break;
+            const int c = (int)((spec->n + nzc - 1) / nzc);
+            if (c >= 4 && std::find(z.begin(), z.end(), c) == z.end()) z.push_back(c);
+        }
+        if (z.empty()) z.push_back(spec->n);
+        return z;
+    };
     const TileChoice before = ctx->tuning.choose(spec->precision, spec->ndim, spec->n, 1);
     const bool had_timing = ctx->timing;
     const int64_t l0 = ctx->t_launches;
@@ -989,7 +1004,7 @@ int ofm_autotune(ofm_ctx* ctx, const ofm_solve_spec* spec, ofm_state_view* st, i
     int tried = 0;
     ofm_qoi q;
     for (int i = 0; i < nt && rc == OFM_OK; ++i)
-        for (int z : zcs) {
+        for (int z : zchunks(tiles[i][0], tiles[i][1])) {
             ctx->tuning.set(spec->precision, spec->ndim, spec->n, TileChoice{ tiles[i][0], tiles[i][1], z, 2 });
             ctx->timing = true;
             ctx->t_launches = 0;

@@ -20,6 +20,9 @@ bool tile_supported(int precision, int ndim, int tx, int ty);
 // compiled tile shapes of (precision, ndim): up to cap (tx, ty) pairs; returns the count
 int tile_list(int precision, int ndim, int (*out)[2], int cap);
 hipError_t launch_stage(int precision, int ndim, int tx, int ty, const LaunchArgs& a, int stage, hipStream_t s);
+// workgroups of the (third-stage) stage kernel of a tile that fit on one CU
+// at once (0 if unknown)
+int stage_blocks_per_cu(int precision, int ndim, int tx, int ty, int order);
 hipError_t launch_reduce(int precision, int ndim, int tx, int ty, const LaunchArgs& a, hipStream_t s);
 hipError_t launch_finalize(const SampleDesc* desc, SampleState* state, const TilePartial* part, int n_samples,
                            int initial, double* dt_log, int64_t dt_log_len, hipStream_t s);

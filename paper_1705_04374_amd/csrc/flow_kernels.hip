@@ -1230,6 +1230,28 @@ hipError_t launch_stage(int precision, int ndim, int tx, int ty, const LaunchArg
     return hipErrorInvalidValue;
 }
 
+template <typename T, int ND, int TX, int TY>
+static int stage_blocks_per_cu_t(int order)
+{
+    int b = 0;
+    const void* f = order == 3 ? reinterpret_cast<const void*>(&stage_kernel<T, ND, TX, TY, 2, 3>)
+                               : reinterpret_cast<const void*>(&stage_kernel<T, ND, TX, TY, 2, 5>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, f, stage_threads<TX, TY>(), 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return b;
+}
+
+int stage_blocks_per_cu(int precision, int ndim, int tx, int ty, int order)
+{
+#define X(T, ND, TX, TY) \
+    if ((precision == OFM_F64) == (sizeof(T) == 8) && ndim == ND && tx == TX && ty == TY) return stage_blocks_per_cu_t<T, ND, TX, TY>(order);
+    OFM_FOR_TILES(X)
+#undef X
+    return 0;
+}
+
 hipError_t launch_reduce(int precision, int ndim, int tx, int ty, const LaunchArgs& a, hipStream_t s)
 {
 #define X(T, ND, TX, TY) \
