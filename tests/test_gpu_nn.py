@@ -9,9 +9,10 @@ Two bars on outputs and gradients:
     intermediate activation, accumulated in float on one side and in double
     on the other, lands on different sides of a bf16 rounding midpoint: that
     operand then differs by one bf16 ulp (2^-8 relative) and moves the
-    entries it feeds by up to 2^-8 of that one term.  RTOL = 1e-2 and
-    ATOL = 1e-3 bound such flips; the largest element-wise deviations seen
-    are printed."""
+    entries it feeds by up to 2^-8 of that one term.  RTOL = 1e-3 and
+    ATOL = 1e-4 leave room for such flips (the largest deviation measured on
+    these problems is 4.6e-6 of a tensor's scale, in the W2 gradient); the
+    largest element-wise deviations are printed."""
 import sys
 
 import numpy as np
@@ -66,7 +67,7 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-30))
 
 
-RTOL, ATOL = 1e-2, 1e-3
+RTOL, ATOL = 1e-3, 1e-4
 
 
 def elementwise(name, got, ref, rtol=RTOL, atol=ATOL):
