@@ -183,13 +183,42 @@ def nn_bench(a):
     }
 
 
+def host_cpu():
+    """(model name, cores this process may run on, logical CPUs of the host)."""
+    import subprocess
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if model is None and os.path.exists("/proc/cpuinfo"):
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    return model, usable, os.cpu_count()
+
+
 def cpu_baseline(cfg, bub):
     """Serial FP64 oracle on P host cores, each advancing its own 64^3 box of
     the same 256^3 cloud by 4 steps (the rate counts every box cell; cells
-    near the box sides see box ghosts, the arithmetic per cell is the same)."""
+    near the box sides see box ghosts, the arithmetic per cell is the same).
+    P = the cores this process may run on, at most the job's share of the
+    host given by OMP_NUM_THREADS when that is set (a shared GPU host gives
+    each GPU's job a fixed share of its cores)."""
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
-    P = min(os.cpu_count() or 1, 16)
+    model, usable, logical = host_cpu()
+    share = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    P = max(1, min(usable, share) if share > 0 else usable)
     n = cfg["n"]
     b = 64
     nst = 4
@@ -209,7 +238,9 @@ def cpu_baseline(cfg, bub):
     step_s = max(r[1] for r in res)
     return dict(value=cells / step_s, unit="cell-updates/s", cores=P, kind="oracle",
                 sample="%d processes x one %d^3 box of the %d^3 500-bubble cloud, %d FP64 steps each "
-                       "(init excluded), wall %.1f s" % (P, b, n, nst, wall))
+                       "(init excluded), wall %.1f s" % (P, b, n, nst, wall),
+                per_core=cells / step_s / P, cpu_model=model, cores_usable=usable, host_logical_cpus=logical,
+                job_core_share=share or None)
 
 
 def _cpu_box(args):

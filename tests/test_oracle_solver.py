@@ -737,3 +737,25 @@ def test_box_steps_match_full_domain_inside():
     lo2, ln2 = (0, 0, 0), (20, 20, 20)
     B2 = F.box_steps(c, bub, (lo2, ln2), dts)
     assert np.array_equal(B2[:, :11, :11, :11], U1[:, :11, :11, :11])
+
+
+def test_stored_collapse_qois_are_the_oracles():
+    """The golden file of whole-collapse QoIs (written by
+    tests/golden/make_collapse_golden.py) matches the oracle as it stands:
+    one 2-D sample recomputed to the end time, and the stored spreads are
+    those of its stored perturbed runs."""
+    from workloads.configs import MASTER_SEED, t_end
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "collapse_qoi.json")))
+    case = [c for c in gold["cases"] if (c["cloud"], c["n"], c["term"], c["index"]) == ("cloud2d", 32, 0, 4)][0]
+    cfg = solver_config("cloud2d", 32)
+    bub = sample_cloud(cloud_spec("cloud2d"), MASTER_SEED, 0, 4)
+    r = F.solve(cfg, bub, t_end=t_end("cloud2d"))
+    assert case["t_end"] == t_end("cloud2d")
+    for k in ("p_max", "t_at_max", "p_sensor", "gas_min", "c_max"):
+        assert math.isclose(r[k], case["qoi"][k], rel_tol=1e-13), k
+    assert r["steps"] == case["qoi"]["steps"] and r["argmax"] == case["qoi"]["argmax"]
+    for c in gold["cases"]:
+        for kind, runs in c["perturbed"].items():
+            for k in ("p_max", "c_max"):
+                s = max(abs(x[k] - c["qoi"][k]) / abs(c["qoi"][k]) for x in runs)
+                assert s == c["spread"][kind][k]
