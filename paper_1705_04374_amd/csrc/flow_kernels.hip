@@ -621,6 +621,49 @@ stage_kernel(LaunchArgs a)
 
     const T beta = (T)(kFarFieldSigma * d.h);     // far-field relaxation fraction
     // load plane gz (with halo) into sW as primitives
+    // A plane with its halo in two parts: the loads of this thread's cells of
+    // it (at most PK) into registers, and their conversion into sW.  In
+    // the 3-D float first stage the loads of plane p+1 are issued before the
+    // x-y work of plane p and converted at plane p+1, so that their latency
+    // hides under that work (the other stages and double have no registers
+    // to spare: they would spill).
+    constexpr int PK = (HX * HY + NT - 1) / NT;
+    constexpr bool PREFETCH = ND == 3 && sizeof(T) == 4 && STAGE == 0;
+    auto plane_fetch = [&](int gz, T (&pf)[PK][NV]) {
+        const int64_t zoff = (int64_t)bc_map(gz, ND == 3 ? n : 1, bc) * plane;
+#pragma unroll
+        for (int k = 0; k < PK; ++k) {
+            const int e = tid + k * NT;
+            if (e < HX * HY) {
+                const int hy = e / HX, hx = e % HX;
+                const int cx = bc_map(x0 + hx - 3, n, bc);
+                const int cy = ND >= 2 ? bc_map(y0 + hy - 3, n, bc) : 0;
+                const int64_t idx = zoff + (int64_t)cy * n + cx;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) pf[k][v] = ua[v * ncell + idx];
+            }
+        }
+    };
+    auto plane_store = [&](const T (&pf)[PK][NV]) {
+#pragma unroll
+        for (int k = 0; k < PK; ++k) {
+            const int e = tid + k * NT;
+            if (e < HX * HY) {
+                const int hy = e / HX, hx = e % HX;
+                const int rx = x0 + hx - 3, ry = ND >= 2 ? y0 + hy - 3 : 0;
+                T w[NV];
+                to_prim<T, ND>(ph, pf[k], w);
+                if (bc == OFM_BC_CHARACTERISTIC) {
+                    // ghosts outside one domain side (corner ghosts are never read)
+                    const bool ox = rx < 0 || rx >= n, oy = ND >= 2 && (ry < 0 || ry >= n);
+                    if (ox != oy) char_ghost<T, ND>(ph, w, ox ? 0 : 1, (ox ? rx : ry) < 0 ? -1 : 1, beta);
+                }
+#pragma unroll
+                for (int v = 0; v < NV; ++v) sW[(v * HY + hy) * HX + hx] = w[v];
+            }
+        }
+    };
+    // without prefetch: one cell at a time (fewer registers live at once)
     auto load_plane = [&](int gz) {
         const int64_t zoff = (int64_t)bc_map(gz, ND == 3 ? n : 1, bc) * plane;
         for (int e = tid; e < HX * HY; e += NT) {
@@ -848,6 +891,7 @@ stage_kernel(LaunchArgs a)
         const int cxg = min(gx, n - 1), cyg = min(gy, n - 1);
         const int64_t col = (int64_t)cyg * n + cxg;    // (clamped) column of this thread
         T q[5][NV];                                    // primitives of planes p-1..p+3
+        T pf[PK][NV];                                  // this thread's cells of the next plane (prefetch)
         T ep[NV];                                      // upper z edge of cell p
         T fz_lo[NV + 1];                               // flux through face p-1/2
         // One loop body does all the work (so that every edge and face is
@@ -878,10 +922,17 @@ stage_kernel(LaunchArgs a)
             T xy[NV + 1];
             if (xy_work) {
                 if constexpr (!SPLIT) __syncthreads();   // sW is the joint pass's face-flux area
-                load_plane(p);
+                if constexpr (PREFETCH) {
+                    plane_store(pf);                     // plane p, loaded one plane ahead
+                    if (p < z1) plane_fetch(p + 1, pf);
+                } else {
+                    load_plane(p);
+                }
                 __syncthreads();
                 plane_xy(xy);
                 if (!early) load_cell();
+            } else if (PREFETCH && p == z0 - 1) {
+                plane_fetch(z0, pf);
             }
 #pragma unroll
             for (int k = 0; k < 4; ++k)
