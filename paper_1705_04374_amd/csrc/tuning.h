@@ -30,11 +30,12 @@ struct Tuning {
         if (it != table.end()) return it->second;
         TileChoice t;
         if (ndim == 3) {
-            // measured fastest at 256^3 (float: 16 x 16 tiles of 16 planes;
-            // double: 16 x 8 tiles of 64 planes)
+            // the autotuner's picks on the 500-bubble cloud: float 16 x 16
+            // tiles of 16 planes up to 256^3, double 16 x 14 tiles of 16
+            // planes; both 16 x 14 tiles of 32 planes at 512^3 and above
             t.tx = 16;
-            t.ty = precision == 1 ? 8 : 16;
-            t.zchunk = precision == 1 && maxn >= 256 ? 64 : 16;
+            t.ty = precision == 1 || maxn >= 512 ? 14 : 16;
+            t.zchunk = maxn >= 512 ? 32 : 16;
         } else if (ndim == 2) {
             t.tx = 16;
             t.ty = 14;
