@@ -407,11 +407,17 @@ int ofm_mlmc_merge_moments(ofm_ctx* ctx, int32_t n_terms, const double* a, const
  * variance of level l-1 (term l-1's fine variance), the members'
  * correlation is term l-1's, and the fine variance is set so that
  * Var_f + Var_c - 2 Cov equals the inferred value (a valid covariance; at
- * least (1 - rho^2) Var_c).  v_hat [dev] L+1 doubles:
+ * least the smallest value that correlation allows, (1 - rho^2) Var_c for
+ * rho >= 0, Var_c for rho < 0).  Terms l >= max(first, 1) with at least two
+ * but fewer than m_floor samples keep the inferred value as a floor of their
+ * difference variance (App. A.1: their few samples refine the inference):
+ * where Var_f + Var_c - 2 Cov is below it, Cov is lowered to
+ * (Var_f + Var_c - v_hat) / 2, at least -sqrt(Var_f Var_c); m_floor <= 2
+ * leaves them as measured.  v_hat [dev] L+1 doubles:
  * exp of the fitted line for l = first..L, 0 below.  flag [dev] 1 int: 0, or
  * OFM_ESINGULAR when fewer than two terms qualify (then v_hat is 0 and mom
- * unchanged).  1 <= L <= 31, 0 <= first <= L.  Asynchronous. */
-int ofm_ofmlmc_fit_indicators(ofm_ctx* ctx, int32_t L, int32_t first, double* mom, double* v_hat,
+ * unchanged).  1 <= L <= 31, 0 <= first <= L, m_floor >= 0.  Asynchronous. */
+int ofm_ofmlmc_fit_indicators(ofm_ctx* ctx, int32_t L, int32_t first, int32_t m_floor, double* mom, double* v_hat,
                               int32_t* flag, void* stream);
 
 /* ---- learned control variate (not in the paper) ----------------------------

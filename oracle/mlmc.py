@@ -228,6 +228,28 @@ def infer_missing_terms(mom: list, v_hat, first: int = 1):
     return mom
 
 
+def refine_few_sample_terms(mom: list, v_hat, first: int = 1, m_floor: int = 2):
+    """Terms l >= max(first, 1) with at least two but fewer than m_floor
+    samples keep the fit's inferred difference variance as a floor: their own
+    estimate from so few samples refines the inferred value (App. A.1: further
+    samples give a more accurate inference), it does not replace it.  The
+    difference variance becomes max(measured, v_hat[l]) by lowering the
+    covariance C of the two members (their variances Vf, Vc stay the measured
+    ones), C' = (Vf + Vc - V') / 2, at least -sqrt(Vf Vc) (a valid
+    covariance: V' at most (sqrt(Vf) + sqrt(Vc))^2).  mom: list of
+    term_moments dicts, updated in place."""
+    for l in range(max(first, 1), len(mom)):
+        m = mom[l]
+        if not (2 <= m["M"] < m_floor):
+            continue
+        v = m["Vf"] + m["Vc"] - 2.0 * m["C"]
+        if not (v_hat[l] > v):
+            continue
+        c = 0.5 * (m["Vf"] + m["Vc"] - v_hat[l])
+        m["C"] = max(c, -math.sqrt(m["Vf"] * m["Vc"]))
+    return mom
+
+
 def mc_samples(var_L: float, eps: float) -> int:
     """Plain Monte Carlo sample count for error eps at the finest level,
     eq. (speedup) with the square of the ratio (the error of a mean of M

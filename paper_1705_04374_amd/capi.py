@@ -139,7 +139,7 @@ def lib():
         L.ofm_ofmlmc_errors.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.ofm_ofmlmc_estimate.argtypes = [vp, i32, vp, vp, vp, vp]
         L.ofm_ofmlmc_optimal_M.argtypes = [vp, i32, vp, vp, vp, i32, C.c_double, vp, vp, vp]
-        L.ofm_ofmlmc_fit_indicators.argtypes = [vp, i32, i32, vp, vp, vp, vp]
+        L.ofm_ofmlmc_fit_indicators.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp]
         L.ofm_mlmc_merge_moments.argtypes = [vp, i32, vp, vp, vp, vp]
         L.ofm_tune_set.argtypes = [vp, i32, i32, i32, i32, i32, i32, i32]
         L.ofm_tune_get.argtypes = [vp, i32, i32, i32, C.POINTER(TuneResult)]
@@ -391,8 +391,8 @@ def ofm_mlmc_merge_moments(ctx: Context, a, b, out, stream=None):
     ctx.check(lib().ofm_mlmc_merge_moments(ctx.h, a.shape[0], _dptr(a), _dptr(b), _dptr(out), _stream(stream)))
 
 
-def ofm_ofmlmc_fit_indicators(ctx: Context, L: int, first: int, mom, v_hat, flag, stream=None):
-    ctx.check(lib().ofm_ofmlmc_fit_indicators(ctx.h, L, first, _dptr(mom), _dptr(v_hat), _dptr(flag),
+def ofm_ofmlmc_fit_indicators(ctx: Context, L: int, first: int, mom, v_hat, flag, stream=None, m_floor: int = 2):
+    ctx.check(lib().ofm_ofmlmc_fit_indicators(ctx.h, L, first, m_floor, _dptr(mom), _dptr(v_hat), _dptr(flag),
                                               _stream(stream)))
 
 

@@ -1120,14 +1120,14 @@ int ofm_mlmc_merge_moments(ofm_ctx* ctx, int32_t n_terms, const double* a, const
     return OFM_OK;
 }
 
-int ofm_ofmlmc_fit_indicators(ofm_ctx* ctx, int32_t L, int32_t first, double* mom, double* v_hat, int32_t* flag,
-                              void* stream)
+int ofm_ofmlmc_fit_indicators(ofm_ctx* ctx, int32_t L, int32_t first, int32_t m_floor, double* mom, double* v_hat,
+                              int32_t* flag, void* stream)
 {
     if (!ctx) return fail(nullptr, OFM_EINVAL, "null context");
-    if (L < 1 || L > 31 || first < 0 || first > L || !mom || !v_hat || !flag)
+    if (L < 1 || L > 31 || first < 0 || first > L || m_floor < 0 || !mom || !v_hat || !flag)
         return fail(ctx, OFM_EINVAL, "ofm_ofmlmc_fit_indicators: bad arguments");
     HIPCHK(ctx, hipSetDevice(ctx->device));
-    HIPCHK(ctx, launch_fit(L, first, mom, v_hat, flag, (hipStream_t)stream));
+    HIPCHK(ctx, launch_fit(L, first, m_floor, mom, v_hat, flag, (hipStream_t)stream));
     return OFM_OK;
 }
 

@@ -39,7 +39,7 @@ hipError_t launch_coefficients(int L, const double* mom, const double* W, double
                                hipStream_t s);
 hipError_t launch_errors(int L, const double* mom, const double* alpha, double* sig, double* eps2, hipStream_t s);
 hipError_t launch_estimate(int L, const double* mom, const double* alpha, double* E, hipStream_t s);
-hipError_t launch_fit(int L, int first, double* mom, double* vhat, int32_t* flag, hipStream_t s);
+hipError_t launch_fit(int L, int first, int m_floor, double* mom, double* vhat, int32_t* flag, hipStream_t s);
 hipError_t launch_merge(int n_terms, const double* a, const double* b, double* out, hipStream_t s);
 hipError_t launch_optimal_M(int L, const double* sig, const double* W, const int64_t* have, int mode,
                             double target, int64_t* out, int32_t* flag, hipStream_t s);

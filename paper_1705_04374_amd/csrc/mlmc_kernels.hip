@@ -167,9 +167,12 @@ __global__ void optimal_M_kernel(int L, const double* sig, const double* W, cons
 // two samples get their moments from the fit: the coarse member takes the
 // variance of level l-1 (term l-1's fine variance Vc), the members'
 // correlation rho is that of term l-1, and the fine member's deviation s
-// gives the inferred difference variance s^2 + Vc - 2 rho s sqrt(Vc).  One
-// thread: L is a handful of terms.
-__global__ void fit_kernel(int L, int first, double* mom, double* vhat, int32_t* flag)
+// gives the inferred difference variance s^2 + Vc - 2 rho s sqrt(Vc).  Terms
+// with at least two but fewer than m_floor samples keep the inferred value as
+// a floor of their difference variance (their few samples refine it, App.
+// A.1): the covariance is lowered to (Vf + Vc - vhat) / 2, at least
+// -sqrt(Vf Vc).  One thread: L is a handful of terms.
+__global__ void fit_kernel(int L, int first, int m_floor, double* mom, double* vhat, int32_t* flag)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double S = 0.0, Sx = 0.0, Sy = 0.0, Sxx = 0.0, Sxy = 0.0;
@@ -213,6 +216,14 @@ __global__ void fit_kernel(int L, int first, double* mom, double* vhat, int32_t*
         m[3] = s * s;
         m[5] = rho * s * sc;
     }
+    // terms with 2 <= M < m_floor: the inferred value as a floor
+    for (int l = first > 1 ? first : 1; l <= L; ++l) {
+        double* m = mom + 6 * l;
+        if (!(m[0] >= 2.0 && m[0] < (double)m_floor)) continue;
+        const double v = m[3] + m[4] - 2.0 * m[5];
+        if (!(vhat[l] > v)) continue;
+        m[5] = fmax(0.5 * (m[3] + m[4] - vhat[l]), -sqrt(m[3] * m[4]));
+    }
     *flag = 0;
 }
 
@@ -252,9 +263,9 @@ hipError_t launch_merge(int n_terms, const double* a, const double* b, double* o
     return hipGetLastError();
 }
 
-hipError_t launch_fit(int L, int first, double* mom, double* vhat, int32_t* flag, hipStream_t s)
+hipError_t launch_fit(int L, int first, int m_floor, double* mom, double* vhat, int32_t* flag, hipStream_t s)
 {
-    hipLaunchKernelGGL(fit_kernel, dim3(1), dim3(64), 0, s, L, first, mom, vhat, flag);
+    hipLaunchKernelGGL(fit_kernel, dim3(1), dim3(64), 0, s, L, first, m_floor, mom, vhat, flag);
     return hipGetLastError();
 }
 

@@ -342,7 +342,8 @@ class OFMLMC:
         the geometric decay of the solver's level differences)."""
         return 2 if self.net is not None else 1
 
-    def evaluate(self, W, classical: bool = False, qoi: str | None = None, fit: bool = False) -> dict:
+    def evaluate(self, W, classical: bool = False, qoi: str | None = None, fit: bool = False,
+                 m_floor: int = 2) -> dict:
         """Estimator on the samples so far: for the driver's QoI, or for
         another QoI of the same samples (the ledger keeps them all).
         fit: infer the level-difference variances by the fit of App. A.1
@@ -355,7 +356,7 @@ class OFMLMC:
                            c=[self.value(self.ledger.have(k, i), "c", qoi) for i in range(self.count[k])],
                            ok=keep[k]["ok"]) for k in range(L + 1)]
             try:
-                return self.evaluate(W, classical, fit=fit)
+                return self.evaluate(W, classical, fit=fit, m_floor=m_floor)
             finally:
                 self.q = keep
         mom = self.moments()
@@ -363,7 +364,7 @@ class OFMLMC:
         if fit and L - self.fit_first() >= 1:
             vh = torch.zeros(L + 1, dtype=torch.float64, device="cuda")
             ff = torch.zeros(1, dtype=torch.int32, device="cuda")
-            capi.ofm_ofmlmc_fit_indicators(self.ctx, L, self.fit_first(), mom, vh, ff)
+            capi.ofm_ofmlmc_fit_indicators(self.ctx, L, self.fit_first(), mom, vh, ff, m_floor=m_floor)
             torch.cuda.synchronize()
             v_hat, fit_flag = vh.cpu().tolist(), int(ff.item())
         Wd = torch.tensor(W, dtype=torch.float64, device="cuda")
@@ -409,7 +410,8 @@ class OFMLMC:
         eq. (warmup) from W_model (relative cost per term).  max_samples:
         optional cap per term (None entries = no cap).  fit: one warm-up
         sample on the finest term and its variances inferred from the lower
-        terms (App. A.1) until it has two."""
+        terms (App. A.1) until it has two; below min_samples, the inferred
+        difference variance stays a floor of a term's measured one."""
         log = log or self.log
         L = self.L
         if min_samples < 2 and not fit:
@@ -428,7 +430,7 @@ class OFMLMC:
         for it in range(max_iter):
             self.sample_terms([max(0, target[k] - self.count[k]) for k in range(L + 1)])
             W = self.work()
-            res = self.evaluate(W, fit=fit)
+            res = self.evaluate(W, fit=fit, m_floor=min_samples)
             tau = rel_tol * abs(res["E"])
             res.update(iteration=it, tau=tau, counts=list(self.count), seconds=time.perf_counter() - t_start,
                        sample_seconds=list(self.time))

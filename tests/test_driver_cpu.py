@@ -106,14 +106,28 @@ def test_fit_warmup_takes_one_finest_sample(tmp_path, monkeypatch):
                            seed=MASTER_SEED, log=lambda *a: None)
         seen = {}
 
-        def fake_eval(W, classical=False, qoi=None, fit=False, mc=mc):
+        def fake_eval(W, classical=False, qoi=None, fit=False, m_floor=2, mc=mc):
             seen["fit"] = fit
+            seen["m_floor"] = m_floor
             return dict(E=1.0, eps=0.0, alpha=[1.0] * 4, sigma_t2=[0.0] * 4, M=list(mc.count), fit_flag=0)
 
         monkeypatch.setattr(mc, "evaluate", fake_eval)
         mc.run(rel_tol=0.01, W_model=W_model, fit=fit)
         # W_L / W_l / 2^(L - l): 576/1/8 = 72, 576/9/4 = 16, 576/72/2 = 4, 1
         assert mc.count == [72, 16, 4, last] and seen["fit"] is fit
+        assert seen["m_floor"] == 2
+    # with a sample floor above two, the fit keeps the inferred difference
+    # variance as a floor of the terms below it: the floor reaches the fit
+    mc = driver.OFMLMC(None, cfg, cloud_spec("cloud2d"), [16, 32, 64, 128], "f32", t_end=1e-4,
+                       seed=MASTER_SEED, log=lambda *a: None)
+
+    def fake_eval6(W, classical=False, qoi=None, fit=False, m_floor=2, mc=mc):
+        seen["m_floor"] = m_floor
+        return dict(E=1.0, eps=0.0, alpha=[1.0] * 4, sigma_t2=[0.0] * 4, M=list(mc.count), fit_flag=0)
+
+    monkeypatch.setattr(mc, "evaluate", fake_eval6)
+    mc.run(rel_tol=0.01, W_model=W_model, fit=True, min_samples=6)
+    assert mc.count == [72, 16, 6, 1] and seen["m_floor"] == 6
 
 
 def test_term_without_variance_is_not_converged(tmp_path, monkeypatch):
@@ -132,7 +146,7 @@ def test_term_without_variance_is_not_converged(tmp_path, monkeypatch):
                            seed=MASTER_SEED, log=lambda *a: None)
         calls = []
 
-        def fake_eval(W, classical=False, qoi=None, fit=False, mc=mc, fit_flag=fit_flag):
+        def fake_eval(W, classical=False, qoi=None, fit=False, m_floor=2, mc=mc, fit_flag=fit_flag):
             calls.append(list(mc.count))
             # every term reports a tiny error: only the missing variance can keep the loop going
             return dict(E=1.0, eps=1e-9, alpha=[1.0] * 4, sigma_t2=[0.0] * 4, M=list(mc.count),

@@ -177,6 +177,46 @@ def test_indicator_fit_completion_with_signed_correlation_below(ctx, C1):
             assert abs(m[3, j] - refs[3][k]) <= 1e-12 * max(abs(refs[3][k]), 1e-300), (V2, k, m[3, j], refs[3][k])
 
 
+@pytest.mark.parametrize("m_floor", [2, 3, 6])
+def test_indicator_fit_keeps_the_inferred_variance_as_a_floor(ctx, m_floor):
+    """Terms with at least two but fewer than m_floor samples keep the
+    inferred difference variance as a floor of their measured one (App.
+    A.1): the device result equals the oracle's fit, completion and
+    refinement of the same moments (<= 1e-12), for a measured variance below
+    the inferred one, one whose inferred value needs a covariance beyond
+    -sqrt(Vf Vc), and one above it (unchanged)."""
+    import torch
+    from paper_1705_04374_amd import capi
+    for V3 in (1e-4, 1e-9, 50.0):
+        rows = [[400.0, 1.0, 0.0, 4.0, 0.0, 0.0], [100.0, 2.0, 1.0, 1.0, 1.0, 0.8],
+                [30.0, 3.0, 2.0, 0.5, 0.5, 0.45], [4.0, 4.0, 3.0, 0.3 + V3, 0.3, 0.3],
+                [1.0, 5.0, 4.0, 0.0, 0.0, 0.0]]
+        if V3 == 1e-9:
+            rows[3][3:6] = [1e-6, 1e-6, 1e-6]      # tiny members: the bound binds
+        mom = torch.tensor(rows, dtype=torch.float64, device="cuda")
+        refs = [dict(M=r[0], mean_f=r[1], mean_c=r[2], Vf=r[3], Vc=r[4], C=r[5]) for r in rows]
+        v_ref, ok = O.fit_indicators([r["M"] for r in refs], [r["Vf"] + r["Vc"] - 2 * r["C"] for r in refs], 1)
+        assert ok
+        O.infer_missing_terms(refs, v_ref, 1)
+        O.refine_few_sample_terms(refs, v_ref, 1, m_floor)
+        v_hat = torch.full((5,), -1.0, dtype=torch.float64, device="cuda")
+        flag = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+        capi.ofm_ofmlmc_fit_indicators(ctx, 4, 1, mom, v_hat, flag, m_floor=m_floor)
+        assert flag.item() == 0
+        np.testing.assert_allclose(v_hat.cpu().numpy(), v_ref, rtol=1e-12, atol=0)
+        m = mom.cpu().numpy()
+        for l in range(5):
+            for j, k in ((3, "Vf"), (4, "Vc"), (5, "C")):
+                assert abs(m[l, j] - refs[l][k]) <= 1e-12 * max(abs(refs[l][k]), 1e-300), (V3, l, k)
+        v3 = m[3, 3] + m[3, 4] - 2 * m[3, 5]
+        if m_floor > 4 and V3 != 50.0:
+            # refined: at the inferred value, or as close as a covariance allows
+            assert v3 >= min(v_ref[3], (np.sqrt(m[3, 3]) + np.sqrt(m[3, 4])) ** 2) * (1 - 1e-12)
+            assert m[3, 5] >= -np.sqrt(m[3, 3] * m[3, 4]) * (1 + 1e-12)
+        else:
+            assert abs(v3 - (rows[3][3] + rows[3][4] - 2 * rows[3][5])) <= 1e-15 * max(1.0, v3)
+
+
 def test_merged_shard_moments_match_the_whole(ctx):
     """Per-shard moments merged on the device (the reduction of a per-GPU
     all-reduce) equal the moments of all samples and the oracle's merge."""

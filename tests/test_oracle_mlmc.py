@@ -345,3 +345,34 @@ def test_merged_shard_moments_equal_the_moments_of_the_union():
     # two single samples: the variance of two values
     one = O.merge_moments(O.term_moments([1.0], [2.0]), O.term_moments([4.0], [0.0]))
     assert one["M"] == 2 and one["Vf"] == 4.5 and one["Vc"] == 2.0 and one["C"] == -3.0
+
+
+def test_few_sample_terms_keep_the_inferred_variance_as_a_floor():
+    """A term with 2 <= M < floor samples: its difference variance becomes
+    max(measured, inferred) by lowering the members' covariance; a larger
+    measured value, a term at the floor, or one below the fit's first term is
+    left as measured; the covariance stays valid (|C| <= sqrt(Vf Vc))."""
+    def terms():
+        return [dict(M=100, Vf=4.0, Vc=0.0, C=0.0), dict(M=20, Vf=1.0, Vc=1.2, C=0.9),
+                dict(M=3, Vf=2.0, Vc=1.0, C=1.3)]
+    # measured V = 2 + 1 - 2.6 = 0.4 < 0.9 inferred: raised to 0.9
+    mom = O.refine_few_sample_terms(terms(), [0.0, 0.5, 0.9], first=1, m_floor=8)
+    m = mom[2]
+    assert math.isclose(m["Vf"] + m["Vc"] - 2 * m["C"], 0.9, rel_tol=1e-15)
+    assert (m["Vf"], m["Vc"]) == (2.0, 1.0) and m["C"] ** 2 <= m["Vf"] * m["Vc"]
+    assert mom[1] == terms()[1]                              # 20 >= floor 8: untouched
+    # an inferred value beyond what a covariance allows: the largest valid one
+    mom = O.refine_few_sample_terms(terms(), [0.0, 0.5, 50.0], first=1, m_floor=8)
+    assert math.isclose(mom[2]["C"], -math.sqrt(2.0), rel_tol=1e-15)
+    assert math.isclose(mom[2]["Vf"] + mom[2]["Vc"] - 2 * mom[2]["C"], (math.sqrt(2.0) + 1.0) ** 2, rel_tol=1e-15)
+    # measured above the inferred value, at the floor, or below `first`: unchanged
+    assert O.refine_few_sample_terms(terms(), [0.0, 0.5, 0.1], 1, 8) == terms()
+    assert O.refine_few_sample_terms(terms(), [0.0, 0.5, 0.9], 1, 3) == terms()
+    assert O.refine_few_sample_terms(terms(), [0.0, 0.5, 0.9], 3, 8) == terms()
+    # the brute-force minimiser of the error term agrees with the closed form
+    # of V' (the difference variance is linear in C)
+    for Vt in (0.9, 1.7):
+        mom = O.refine_few_sample_terms(terms(), [0.0, 0.5, Vt], 1, 8)
+        Cs = np.linspace(-math.sqrt(2.0), math.sqrt(2.0), 100001)
+        best = Cs[np.argmin(np.abs(3.0 - 2 * Cs - Vt))]
+        assert abs(mom[2]["C"] - best) <= 3e-5
