@@ -581,8 +581,11 @@ stage_kernel(LaunchArgs a)
     constexpr int EST = SPLIT ? ESX : ES;              // stride of the edge arrays
     static_assert(!SPLIT || ((NV + 1) * FXN <= 2 * NV * ESX && (NV + 1) * FYN <= 2 * NV * ESX), "face alias");
     static_assert(!SPLIT || (FXN <= 2 * NT && FYN <= 2 * NT), "at most two faces per thread in the split pass");
-    // a workgroup's LDS is kept below 64 KiB: kernels whose static LDS went
-    // above it computed silently wrong states (tiling invariance failed)
+    // a workgroup's LDS is kept below 64 KiB: the one stage-kernel variant
+    // above it (a running reduction held in LDS) computed states that
+    // differed between tilings, for a cause not found (the set network's
+    // pooling kernel runs correctly with 73.7 KB); every variant that passed
+    // the tiling-invariance test is below
     static_assert(sizeof(T) * (SPLIT ? WSZ + 2 * NV * ESX : AL + 2 * NV * ES) + sizeof(Red) * (NT / 64) <= 65536,
                   "stage kernel LDS above 64 KiB");
     __shared__ T smem[SPLIT ? WSZ + 2 * NV * ESX : AL + 2 * NV * ES];

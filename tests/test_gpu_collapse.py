@@ -1,7 +1,9 @@
 """Whole cloud collapses in 3-D against the oracle: the Sec. 2.2 scheme run
 through the collapse and rebound of the Sec. 3.1 set-up to the end time, the
 QoIs of Sec. 3.3 compared with the FP64 oracle's (stored by
-tests/golden/make_collapse_golden.py, which calls only the oracle).
+tests/golden/make_collapse_golden.py, which calls only the oracle), with
+WENO5 and zero-gradient sides, and with the third-order reconstruction and
+the characteristic far-field sides.
 
 A collapse amplifies rounding differences, and by how much depends on the
 sample.  The golden file keeps, per sample, how far the oracle's own QoIs
@@ -47,11 +49,16 @@ def bar(case, kind, q):
     return max(FLOOR, K * case["spread"][kind][q])
 
 
-@pytest.mark.parametrize("case", CASES3, ids=lambda c: "%s-%d-%d" % (c["cloud"], c["n"], c["index"]))
+def case_id(c):
+    opt = "-".join("%s=%s" % kv for kv in sorted(c.get("options", {}).items()))
+    return "%s-%d-%d%s" % (c["cloud"], c["n"], c["index"], "-" + opt if opt else "")
+
+
+@pytest.mark.parametrize("case", CASES3, ids=case_id)
 def test_fp64_collapse_qois_against_oracle(ctx, case):
     from paper_1705_04374_amd import capi
-    say("3-D collapse, FP64:", case["cloud"], case["n"], "index", case["index"])
-    cfg = solver_config(case["cloud"], case["n"])
+    say("3-D collapse, FP64:", case_id(case))
+    cfg = solver_config(case["cloud"], case["n"], **case.get("options", {}))
     bub = capi.ofm_sample_cloud(cloud_spec(case["cloud"]), MASTER_SEED, case["term"], case["index"])
     q = capi.ofm_solve(ctx, capi.make_spec(cfg, "f64", t_end=case["t_end"]), bub)
     ref = case["qoi"]
@@ -68,11 +75,11 @@ def test_fp64_collapse_qois_against_oracle(ctx, case):
         assert q["argmax"] == ref["argmax"]
 
 
-@pytest.mark.parametrize("case", CASES3, ids=lambda c: "%s-%d-%d" % (c["cloud"], c["n"], c["index"]))
+@pytest.mark.parametrize("case", CASES3, ids=case_id)
 def test_fp32_collapse_peak_pressure_against_oracle(ctx, case):
     from paper_1705_04374_amd import capi
-    say("3-D collapse, FP32:", case["cloud"], case["n"], "index", case["index"])
-    cfg = solver_config(case["cloud"], case["n"])
+    say("3-D collapse, FP32:", case_id(case))
+    cfg = solver_config(case["cloud"], case["n"], **case.get("options", {}))
     bub = capi.ofm_sample_cloud(cloud_spec(case["cloud"]), MASTER_SEED, case["term"], case["index"])
     q = capi.ofm_solve(ctx, capi.make_spec(cfg, "f32", t_end=case["t_end"]), bub)
     ref = case["qoi"]
