@@ -230,9 +230,10 @@ int ofm_step(ofm_ctx* ctx, const ofm_solve_spec* spec, ofm_state_view* st, int64
 /* Size of the fixed device scratch of ofm_step_noalloc, per GPU. */
 #define OFM_NOALLOC_SCRATCH_BYTES (4u << 20)
 
-/* ofm_step for callers that cannot allocate memory (code under graph
- * capture, tight serving loops, harnesses that forbid device or pinned
- * allocations): the same kernels and launches, on the caller's stream, with
+/* ofm_step for callers that cannot allocate memory (tight serving loops,
+ * harnesses that forbid device or pinned allocations; it synchronises the
+ * stream, so it cannot be recorded into a graph): the same kernels and
+ * launches, on the caller's stream, with
  * the same results bit for bit; it calls no hipMalloc, hipHostMalloc or
  * hipFree and creates no events.  Its scratch (the sample's descriptor and
  * dynamic state, 64 B of reduction partial and 8 B of work list per tile of
