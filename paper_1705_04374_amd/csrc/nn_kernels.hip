@@ -149,7 +149,9 @@ __global__ void __launch_bounds__(256) gemm_finish_kernel(const float* __restric
 // are processed 128 at a time: the input layer on the vector units into LDS
 // (bf16), the 128 x 128 layer on the matrix cores, bias + ReLU, then column
 // sums over the rows (fixed order, so a set's result does not depend on the
-// grid).
+// grid).  In the input layer a thread owns one column (its four weights and
+// bias in registers) for half of the chunk's rows, and the chunk's inputs
+// are read from LDS one row at a time by the whole wavefront (a broadcast).
 // ---------------------------------------------------------------------------
 constexpr int HP = 128 + 8;
 
@@ -162,35 +164,49 @@ __global__ void __launch_bounds__(256) phi_pool_kernel(const float* __restrict__
 {
     __shared__ uint16_t sW[128 * HP];   // W2 [n][k]
     __shared__ uint16_t sH[128 * HP];   // h1 chunk [row][k]
-    __shared__ float sW1[128 * 4], sb1[128], sb2[128];
+    __shared__ float4 sX[128];          // the chunk's input rows
+    __shared__ float sb2[128];
     __shared__ float colsum[2][128];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave >> 1, wc = wave & 1;
-    const float* W1 = P + NN_W1;
     for (int e = tid; e < 128 * 128; e += 256) sW[(e >> 7) * HP + (e & 127)] = W2bf[e];
-    for (int e = tid; e < 128 * 4; e += 256) sW1[e] = W1[e];
-    if (tid < 128) { sb1[tid] = P[NN_B1 + tid]; sb2[tid] = P[NN_B2 + tid]; }
+    if (tid < 128) sb2[tid] = P[NN_B2 + tid];
+    // input layer: this thread's column and half of the rows
+    const int ic = tid & 127, ih = (tid >> 7) * 64;
+    const float ib = P[NN_B1 + ic];
+    float iw[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) iw[k] = P[NN_W1 + ic * 4 + k];
     for (int set = blockIdx.x; set < n_sets; set += gridDim.x) {
         const int r0 = offsets[set], r1 = offsets[set + 1];
         float acc_col = 0.f;   // running column sum, thread tid < 128 owns column tid
         for (int c0 = r0; c0 < r1; c0 += 128) {
             __syncthreads();
-            // input layer: thread -> row tid / 2, 64 columns
-            {
-                const int rl = tid >> 1, cb = (tid & 1) * 64;
-                const int r = c0 + rl;
-                float xv[4] = { 0.f, 0.f, 0.f, 0.f };
+            if (tid < 128) {
+                const int r = c0 + tid;
+                float4 xv = make_float4(0.f, 0.f, 0.f, 0.f);
                 if (r < r1) {
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) xv[k] = x[(int64_t)r * 4 + k];
+                    const float* xr = x + (int64_t)r * 4;
+                    xv = make_float4(xr[0], xr[1], xr[2], xr[3]);
                 }
-                for (int c = cb; c < cb + 64; ++c) {
-                    float z = sb1[c];
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) z += xv[k] * sW1[c * 4 + k];
-                    const uint16_t h = r < r1 ? to_bf16(fmaxf(z, 0.f)) : (uint16_t)0;
-                    sH[rl * HP + c] = h;
-                    if (h1_bf && r < r1) h1_bf[(int64_t)r * 128 + c] = h;
+                sX[tid] = xv;
+            }
+            __syncthreads();
+            {
+                const int nr = min(r1 - c0, 128);
+                for (int rl = ih; rl < ih + 64; ++rl) {
+                    uint16_t h = 0;
+                    if (rl < nr) {
+                        const float4 xv = sX[rl];
+                        float z = ib;
+                        z += xv.x * iw[0];
+                        z += xv.y * iw[1];
+                        z += xv.z * iw[2];
+                        z += xv.w * iw[3];
+                        h = to_bf16(fmaxf(z, 0.f));
+                        if (h1_bf) h1_bf[(int64_t)(c0 + rl) * 128 + ic] = h;
+                    }
+                    sH[rl * HP + ic] = h;
                 }
             }
             __syncthreads();
@@ -216,23 +232,32 @@ __global__ void __launch_bounds__(256) phi_pool_kernel(const float* __restrict__
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
             }
             // bias + ReLU + per-column partial sums of this wave's 64 rows
+            // (a chunk of 128 rows needs no row check)
+            const bool full = c0 + 128 <= r1;
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 const int col = wc * 64 + j * 32 + (lane & 31);
                 const float bb = sb2[col];
                 float cs = 0.f;
+                if (full && !z2_out) {
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+                    for (int i = 0; i < 2; ++i)
 #pragma unroll
-                    for (int e = 0; e < 16; ++e) {
-                        const int rl = wr * 64 + i * 32 + mfma_row(e, lane);
-                        const int r = c0 + rl;
-                        const float z = acc[i][j][e] + bb;
-                        if (r < r1) {
-                            cs += fmaxf(z, 0.f);
-                            if (z2_out) z2_out[(int64_t)r * 128 + col] = z;
+                        for (int e = 0; e < 16; ++e) cs += fmaxf(acc[i][j][e] + bb, 0.f);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 2; ++i)
+#pragma unroll
+                        for (int e = 0; e < 16; ++e) {
+                            const int rl = wr * 64 + i * 32 + mfma_row(e, lane);
+                            const int r = c0 + rl;
+                            const float z = acc[i][j][e] + bb;
+                            if (r < r1) {
+                                cs += fmaxf(z, 0.f);
+                                if (z2_out) z2_out[(int64_t)r * 128 + col] = z;
+                            }
                         }
-                    }
+                }
                 cs += __shfl_xor(cs, 32, 64);
                 if (lane < 32) colsum[wr][col] = cs;
             }
