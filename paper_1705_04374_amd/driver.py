@@ -42,6 +42,8 @@ from . import capi
 SAMPLE_OK = capi.SAMPLE_OK
 # stream of the learned level's training samples (no estimator term uses it)
 TRAIN_TERM = 1 << 20
+# stream of the plain Monte Carlo comparator's samples
+MC_TERM = TRAIN_TERM + 1
 
 
 class Fidelity:
@@ -581,6 +583,57 @@ def plain_mc_comparison(mc, res: dict, rel_tol: float, fp64_step_seconds: float,
     return out
 
 
+def plain_mc_run(ctx: capi.Context, cfg: dict, cloud: dict, n: int, precision: str, T: float, seed: int,
+                 count: int, ledger_path: str | None = None, log=print, deadline: float | None = None) -> dict:
+    """Plain Monte Carlo as the comparator of eq. (speedup) runs it: `count`
+    clouds of their own stream, each solved alone to the end time at grid n,
+    one after the other (ofm_solve: no batching, the state resident on the
+    device).  Returns every solve's measured wall seconds and step count, the
+    QoIs' means and sample variances, and the same cost as the comparator's
+    estimate prices it (the solves' mean step count times the seconds per
+    step of a short stepping run, `step_seconds`), so that the estimate can be
+    checked against whole measured solves.  The ledger keeps every finished
+    sample (a stopped run resumes)."""
+    led = Ledger(ledger_path)
+    c = dict(cfg)
+    c["n"] = n
+    spec = capi.make_spec(c, precision, t_end=T)
+    rows = []
+    for i in range(count):
+        r = led.have(MC_TERM, i)
+        if r is None or r.get("n") != n or r.get("precision") != precision:
+            if deadline is not None and rows:
+                if time.time() + max(x["seconds"] for x in rows) > deadline:
+                    raise Deadline("plain MC sample %d" % i)
+            b = capi.ofm_sample_cloud(cloud, seed, MC_TERM, i)
+            t0 = time.perf_counter()
+            q = capi.ofm_solve(ctx, spec, b)
+            sec = time.perf_counter() - t0
+            r = dict(term=MC_TERM, index=i, n=n, precision=precision, seconds=sec, steps=int(q["steps"]),
+                     ok=q["status"] == SAMPLE_OK, qoi={k: float(q[k]) for k in QOIS})
+            led.add([r])
+            log("  plain MC %s %d^3 sample %d: %.2f s, %d steps, p_max %.4e%s" % (
+                precision, n, i, sec, r["steps"], r["qoi"]["p_max"], "" if r["ok"] else " (failed)"))
+        rows.append(r)
+    ok = [r for r in rows if r["ok"]]
+    secs = np.array([r["seconds"] for r in rows])
+    steps = np.array([r["steps"] for r in ok], dtype=np.float64)
+    out = dict(n=n, precision=precision, samples=len(rows), failed=len(rows) - len(ok),
+               seconds=[float(x) for x in secs], steps=[int(x) for x in steps],
+               mean_seconds=float(secs.mean()), min_seconds=float(secs.min()), max_seconds=float(secs.max()),
+               measured_step_seconds=float(secs[[r["ok"] for r in rows]].sum() / max(steps.sum(), 1.0)))
+    for k in QOIS:
+        v = np.array([r["qoi"][k] for r in ok])
+        out[k] = dict(mean=float(v.mean()) if v.size else None,
+                      var=float(np.var(v, ddof=1)) if v.size >= 2 else None)
+    sec = step_seconds(ctx, cfg, cloud, n, precision, seed)
+    out["model_step_seconds"] = sec
+    out["model_seconds_per_sample"] = float(steps.mean()) * sec if steps.size else None
+    if steps.size:
+        out["measured_over_model"] = float(secs[[r["ok"] for r in rows]].mean()) / out["model_seconds_per_sample"]
+    return out
+
+
 def variance_reduction(res: dict, term: int = 1) -> dict:
     """What the learned level gains on a pair term (solver level, network):
     the variance the term would have without the lower member, with the
@@ -613,6 +666,9 @@ WORKLOADS = {
     # terms of "ofmlmc" (same clouds), so the two share one ledger
     "ofmlmc256": dict(cloud="cloud500", levels=[64, 128, 256], n_train=64, count_train=4096, M_nn=65536,
                       precision="f32", ledger="ofmlmc"),
+    # the plain FP64 Monte Carlo comparator itself, capped: independent
+    # clouds solved one at a time to the end time, each solve timed
+    "plainmc": dict(cloud="cloud500", levels=[256], precision="f64", samples=16),
 }
 
 
@@ -632,6 +688,8 @@ def main(argv=None):
     ap.add_argument("--weno-order", type=int, default=5, choices=[3, 5], help="WENO reconstruction order")
     ap.add_argument("--bc", default="zero_gradient", choices=["zero_gradient", "characteristic"],
                     help="domain sides: zero gradient, or the characteristic far field with the p_inf penalty")
+    ap.add_argument("--samples", type=int, default=0, help="plainmc: number of solves (default: the workload's)")
+    ap.add_argument("--n", type=int, default=0, help="plainmc: grid (default: the workload's)")
     ap.add_argument("--time-limit", type=float, default=0.0,
                     help="seconds; batches that would end later are not started (exit status 3, resume later)")
     a = ap.parse_args(argv)
@@ -719,6 +777,12 @@ def _run_workload(a, w, ctx, cloud, T, seed, deadline, log) -> dict:
         for prec in ("f32", "f64"):
             out["sequential_%s_seconds" % prec] = sum(solves[n] * single["%s_%d" % (prec, n)]["seconds"]
                                                       for n in w["levels"])
+    elif a.workload == "plainmc":
+        n = a.n or w["levels"][-1]
+        cfg = scheme(solver_config(w["cloud"], n), a)
+        out["plain_mc"] = plain_mc_run(ctx, cfg, cloud, n, w["precision"], T, seed, a.samples or w["samples"],
+                                       ledger, log=log, deadline=deadline)
+        log("plain MC: %s" % json.dumps({k: v for k, v in out["plain_mc"].items() if k not in ("seconds", "steps")}))
     elif a.workload == "surrogate":
         cfg = scheme(solver_config(w["cloud"], w["n_train"]), a)
         sur, info = train_level(ctx, cloud, cfg, w["n_train"], w["count_train"], T, seed, w["precision"],

@@ -181,3 +181,40 @@ def test_failed_samples_count_against_the_two_sample_floor(tmp_path, monkeypatch
     assert mc.unfilled_terms(res, fit=False) == [1]
     assert mc.unfilled_terms(dict(M=[5, 1], fit_flag=0), fit=True) == []
     assert mc.unfilled_terms(dict(M=[1, 3], fit_flag=0), fit=True) == [0]     # below the fit's first term
+
+
+def test_plain_mc_run_times_each_solve_and_resumes(tmp_path, monkeypatch):
+    """The capped plain Monte Carlo comparator: independent clouds of their
+    own stream, one solve each, every solve timed; the QoIs' mean and sample
+    variance over the solves; the comparator's cost model (mean steps x
+    seconds per step) beside the measured seconds; a rerun reads the ledger
+    and solves only samples it does not hold."""
+    import numpy as np
+    seen = []
+
+    def fake_solve(ctx, spec, bubbles):
+        seen.append([tuple(b) for b in bubbles])
+        return fake_qoi(spec, bubbles)
+
+    monkeypatch.setattr(driver.capi, "ofm_solve", fake_solve)
+    monkeypatch.setattr(driver, "step_seconds", lambda *a, **k: 1e-3)
+    cfg = solver_config("cloud2d", 16)
+    cloud = cloud_spec("cloud2d")
+    led = str(tmp_path / "mc.jsonl")
+    r = driver.plain_mc_run(None, cfg, cloud, 16, "f64", 1e-4, MASTER_SEED, 5, led, log=lambda *a: None)
+    assert len(seen) == 5 and r["samples"] == 5 and r["failed"] == 0 and r["steps"] == [16] * 5
+    assert r["model_seconds_per_sample"] == pytest.approx(16e-3)
+    # every sample is its own cloud, none of them an estimator term's
+    assert len(set(map(tuple, seen))) == 5
+    term0 = [tuple(b) for b in driver.capi.ofm_sample_cloud(cloud, MASTER_SEED, 0, 0)]
+    assert all(s != term0 for s in seen)
+    p = np.array([fake_qoi(type("S", (), {"n": 16})(), [list(b) for b in s])["p_max"] for s in seen])
+    assert r["p_max"]["mean"] == pytest.approx(p.mean(), rel=1e-15)
+    assert r["p_max"]["var"] == pytest.approx(np.var(p, ddof=1), rel=1e-12)
+    assert r["measured_step_seconds"] == pytest.approx(sum(r["seconds"]) / 80.0)
+    # rerun: nothing solved again; a larger count solves only the new samples
+    seen.clear()
+    r2 = driver.plain_mc_run(None, cfg, cloud, 16, "f64", 1e-4, MASTER_SEED, 5, led, log=lambda *a: None)
+    assert seen == [] and r2["p_max"] == r["p_max"] and r2["seconds"] == r["seconds"]
+    r3 = driver.plain_mc_run(None, cfg, cloud, 16, "f64", 1e-4, MASTER_SEED, 7, led, log=lambda *a: None)
+    assert len(seen) == 2 and r3["samples"] == 7 and r3["seconds"][:5] == r["seconds"]
