@@ -584,11 +584,14 @@ def plain_mc_comparison(mc, res: dict, rel_tol: float, fp64_step_seconds: float,
 
 
 def plain_mc_run(ctx: capi.Context, cfg: dict, cloud: dict, n: int, precision: str, T: float, seed: int,
-                 count: int, ledger_path: str | None = None, log=print, deadline: float | None = None) -> dict:
+                 count: int, ledger_path: str | None = None, log=print, deadline: float | None = None,
+                 portion_steps: int = 0) -> dict:
     """Plain Monte Carlo as the comparator of eq. (speedup) runs it: `count`
     clouds of their own stream, each solved alone to the end time at grid n,
-    one after the other (ofm_solve: no batching, the state resident on the
-    device).  Returns every solve's measured wall seconds and step count, the
+    one after the other (no batching, the state resident on the device;
+    ofm_solve, or with portion_steps > 0 the same solve advanced that many
+    steps per call, with a progress line after each portion).  Returns every
+    solve's measured wall seconds and step count, the
     QoIs' means and sample variances, and the same cost as the comparator's
     estimate prices it (the solves' mean step count times the seconds per
     step of a short stepping run, `step_seconds`), so that the estimate can be
@@ -607,7 +610,17 @@ def plain_mc_run(ctx: capi.Context, cfg: dict, cloud: dict, n: int, precision: s
                     raise Deadline("plain MC sample %d" % i)
             b = capi.ofm_sample_cloud(cloud, seed, MC_TERM, i)
             t0 = time.perf_counter()
-            q = capi.ofm_solve(ctx, spec, b)
+            if portion_steps > 0:
+                run = capi.Run(ctx, [spec], [b])
+                try:
+                    while not run.advance(portion_steps):
+                        log("  plain MC %s %d^3 sample %d: %d steps, %.1f s" % (
+                            precision, n, i, run.status()["steps"], time.perf_counter() - t0))
+                    q = run.status()["qoi"][0]
+                finally:
+                    run.close()
+            else:
+                q = capi.ofm_solve(ctx, spec, b)
             sec = time.perf_counter() - t0
             r = dict(term=MC_TERM, index=i, n=n, precision=precision, seconds=sec, steps=int(q["steps"]),
                      ok=q["status"] == SAMPLE_OK, qoi={k: float(q[k]) for k in QOIS})
@@ -780,8 +793,9 @@ def _run_workload(a, w, ctx, cloud, T, seed, deadline, log) -> dict:
     elif a.workload == "plainmc":
         n = a.n or w["levels"][-1]
         cfg = scheme(solver_config(w["cloud"], n), a)
+        # a solve above 256^3 reports its progress every 500 steps
         out["plain_mc"] = plain_mc_run(ctx, cfg, cloud, n, w["precision"], T, seed, a.samples or w["samples"],
-                                       ledger, log=log, deadline=deadline)
+                                       ledger, log=log, deadline=deadline, portion_steps=500 if n > 256 else 0)
         log("plain MC: %s" % json.dumps({k: v for k, v in out["plain_mc"].items() if k not in ("seconds", "steps")}))
     elif a.workload == "surrogate":
         cfg = scheme(solver_config(w["cloud"], w["n_train"]), a)

@@ -218,3 +218,31 @@ def test_plain_mc_run_times_each_solve_and_resumes(tmp_path, monkeypatch):
     assert seen == [] and r2["p_max"] == r["p_max"] and r2["seconds"] == r["seconds"]
     r3 = driver.plain_mc_run(None, cfg, cloud, 16, "f64", 1e-4, MASTER_SEED, 7, led, log=lambda *a: None)
     assert len(seen) == 2 and r3["samples"] == 7 and r3["seconds"][:5] == r["seconds"]
+
+
+def test_plain_mc_run_in_portions(tmp_path, monkeypatch):
+    """Large grids advance each solve in portions (a progress line after
+    each); the QoIs are the run's at its end."""
+    class FakeRun:
+        def __init__(self, ctx, specs, bubbles):
+            self.spec, self.b, self.k = specs[0], bubbles[0], 0
+
+        def advance(self, max_steps):
+            self.k += 1
+            return self.k == 3
+
+        def status(self):
+            return dict(qoi=[fake_qoi(self.spec, self.b)], steps=self.k * 500)
+
+        def close(self):
+            pass
+
+    monkeypatch.setattr(driver.capi, "Run", FakeRun)
+    monkeypatch.setattr(driver.capi, "ofm_solve", lambda *a: pytest.fail("not in portions"))
+    monkeypatch.setattr(driver, "step_seconds", lambda *a, **k: 1e-3)
+    lines = []
+    cfg = solver_config("cloud2d", 16)
+    r = driver.plain_mc_run(None, cfg, cloud_spec("cloud2d"), 16, "f64", 1e-4, MASTER_SEED, 2,
+                            str(tmp_path / "mc.jsonl"), log=lines.append, portion_steps=500)
+    assert r["samples"] == 2 and r["steps"] == [16, 16]
+    assert sum("500 steps" in x for x in lines) == 2 and sum("1000 steps" in x for x in lines) == 2
