@@ -100,8 +100,9 @@ class Deadline(Exception):
 
 
 # cell-steps per second assumed when predicting a batch's duration against a
-# deadline (below the measured rates of the stage kernel)
-PREDICT_RATE = {"f32": 4.0e9, "f64": 1.5e9}
+# deadline (below the measured batched rates: FP32 4.9e9 for mixed 64^3 to
+# 256^3 batches, 5.4-5.7e9 for 512^3; FP64 2.3-2.5e9)
+PREDICT_RATE = {"f32": 4.8e9, "f64": 2.0e9}
 
 
 def state_bytes(ndim: int, n: int, precision: str) -> float:
