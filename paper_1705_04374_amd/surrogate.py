@@ -1,7 +1,7 @@
 """The learned low-fidelity level: a permutation-invariant set network over
 the bubbles of a cloud, trained on QoIs that the solver itself produced, and
 used as the cheapest level of OF-MLMC (its coefficient alpha absorbs its
-error; the solver levels stay the judge).
+error; the solver levels remain the reference that bounds it).
 
 Everything numeric runs in the library's kernels (ofm_nn_*): per-bubble
 features, the fused phi + pool forward on BF16 matrix cores, the backward
