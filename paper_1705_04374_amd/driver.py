@@ -794,7 +794,9 @@ def _run_workload(a, w, ctx, cloud, T, seed, deadline, log) -> dict:
     elif a.workload == "plainmc":
         n = a.n or w["levels"][-1]
         cfg = scheme(solver_config(w["cloud"], n), a)
-        # a solve above 256^3 reports its progress every 500 steps
+        # one ledger per grid (the samples of each grid are kept apart); a
+        # solve above 256^3 reports its progress every 500 steps
+        ledger = os.path.join(a.dir, "ledger_plainmc_%d.jsonl" % n)
         out["plain_mc"] = plain_mc_run(ctx, cfg, cloud, n, w["precision"], T, seed, a.samples or w["samples"],
                                        ledger, log=log, deadline=deadline, portion_steps=500 if n > 256 else 0)
         log("plain MC: %s" % json.dumps({k: v for k, v in out["plain_mc"].items() if k not in ("seconds", "steps")}))
