@@ -727,7 +727,8 @@ def main(argv=None):
         log("stopped before the deadline:", e, "- the ledgers in", a.dir, "resume the run")
         ctx.close()
         sys.exit(3)
-    path = os.path.join(a.dir, "result_%s.json" % a.workload)
+    name = a.workload if a.workload != "plainmc" else "plainmc_%d" % out["plain_mc"]["n"]
+    path = os.path.join(a.dir, "result_%s.json" % name)
     with open(path, "w") as f:
         json.dump(out, f, indent=1, default=float)
     log("wrote", path)
