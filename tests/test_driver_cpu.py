@@ -246,3 +246,33 @@ def test_plain_mc_run_in_portions(tmp_path, monkeypatch):
                             str(tmp_path / "mc.jsonl"), log=lines.append, portion_steps=500)
     assert r["samples"] == 2 and r["steps"] == [16, 16]
     assert sum("500 steps" in x for x in lines) == 2 and sum("1000 steps" in x for x in lines) == 2
+
+
+def test_plainmc_command_line(tmp_path, monkeypatch):
+    """`driver plainmc`: the grid and count from the command line reach the
+    run, each grid keeps its own ledger, and the result file is named by the
+    grid."""
+    seen = {}
+
+    class FakeCtx:
+        def __init__(self, device):
+            pass
+
+        def close(self):
+            pass
+
+    def fake_run(ctx, cfg, cloud, n, precision, T, seed, count, ledger_path, log=print, deadline=None,
+                 portion_steps=0):
+        seen.update(n=n, count=count, ledger=ledger_path, precision=precision, portion=portion_steps)
+        return dict(n=n, samples=count)
+
+    monkeypatch.setattr(driver.capi, "Context", FakeCtx)
+    monkeypatch.setattr(driver, "plain_mc_run", fake_run)
+    out = driver.main(["plainmc", "--n", "512", "--samples", "3", "--dir", str(tmp_path)])
+    assert seen == dict(n=512, count=3, ledger=str(tmp_path / "ledger_plainmc_512.jsonl"), precision="f64",
+                        portion=500)
+    assert out["plain_mc"] == dict(n=512, samples=3)
+    assert json.load(open(tmp_path / "result_plainmc_512.json"))["plain_mc"]["n"] == 512
+    driver.main(["plainmc", "--dir", str(tmp_path)])
+    assert seen["n"] == 256 and seen["count"] == 16 and seen["portion"] == 0
+    assert (tmp_path / "result_plainmc_256.json").exists()
