@@ -391,7 +391,7 @@ def ofm_mlmc_merge_moments(ctx: Context, a, b, out, stream=None):
     ctx.check(lib().ofm_mlmc_merge_moments(ctx.h, a.shape[0], _dptr(a), _dptr(b), _dptr(out), _stream(stream)))
 
 
-def ofm_ofmlmc_fit_indicators(ctx: Context, L: int, first: int, mom, v_hat, flag, stream=None, m_floor: int = 2):
+def ofm_ofmlmc_fit_indicators(ctx: Context, L: int, first: int, m_floor: int, mom, v_hat, flag, stream=None):
     ctx.check(lib().ofm_ofmlmc_fit_indicators(ctx.h, L, first, m_floor, _dptr(mom), _dptr(v_hat), _dptr(flag),
                                               _stream(stream)))
 

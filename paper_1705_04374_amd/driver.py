@@ -367,7 +367,7 @@ class OFMLMC:
         if fit and L - self.fit_first() >= 1:
             vh = torch.zeros(L + 1, dtype=torch.float64, device="cuda")
             ff = torch.zeros(1, dtype=torch.int32, device="cuda")
-            capi.ofm_ofmlmc_fit_indicators(self.ctx, L, self.fit_first(), mom, vh, ff, m_floor=m_floor)
+            capi.ofm_ofmlmc_fit_indicators(self.ctx, L, self.fit_first(), m_floor, mom, vh, ff)
             torch.cuda.synchronize()
             v_hat, fit_flag = vh.cpu().tolist(), int(ff.item())
         Wd = torch.tensor(W, dtype=torch.float64, device="cuda")

@@ -115,7 +115,7 @@ def test_indicator_fit_matches_oracle(ctx, Ms, first):
     O.infer_missing_terms(refs, v_ref, first)
     v_hat = torch.full((L + 1,), -1.0, dtype=torch.float64, device="cuda")
     flag = torch.full((1,), -7, dtype=torch.int32, device="cuda")
-    capi.ofm_ofmlmc_fit_indicators(ctx, L, first, mom, v_hat, flag)
+    capi.ofm_ofmlmc_fit_indicators(ctx, L, first, 2, mom, v_hat, flag)
     assert flag.item() == 0
     np.testing.assert_allclose(v_hat.cpu().numpy(), v_ref, rtol=1e-12, atol=0)
     m = mom.cpu().numpy()
@@ -141,7 +141,7 @@ def test_indicator_fit_needs_two_terms(ctx):
     before = mom.clone()
     v_hat = torch.full((3,), -1.0, dtype=torch.float64, device="cuda")
     flag = torch.zeros(1, dtype=torch.int32, device="cuda")
-    capi.ofm_ofmlmc_fit_indicators(ctx, 2, 1, mom, v_hat, flag)
+    capi.ofm_ofmlmc_fit_indicators(ctx, 2, 1, 2, mom, v_hat, flag)
     assert flag.item() == capi.OFM_ESINGULAR
     assert v_hat.cpu().tolist() == [0.0, 0.0, 0.0]
     assert torch.equal(mom, before)
@@ -169,7 +169,7 @@ def test_indicator_fit_completion_with_signed_correlation_below(ctx, C1):
         O.infer_missing_terms(refs, v_ref, 1)
         v_hat = torch.full((4,), -1.0, dtype=torch.float64, device="cuda")
         flag = torch.full((1,), -7, dtype=torch.int32, device="cuda")
-        capi.ofm_ofmlmc_fit_indicators(ctx, 3, 1, mom, v_hat, flag)
+        capi.ofm_ofmlmc_fit_indicators(ctx, 3, 1, 2, mom, v_hat, flag)
         assert flag.item() == 0
         np.testing.assert_allclose(v_hat.cpu().numpy(), v_ref, rtol=1e-12, atol=0)
         m = mom.cpu().numpy()
@@ -201,7 +201,7 @@ def test_indicator_fit_keeps_the_inferred_variance_as_a_floor(ctx, m_floor):
         O.refine_few_sample_terms(refs, v_ref, 1, m_floor)
         v_hat = torch.full((5,), -1.0, dtype=torch.float64, device="cuda")
         flag = torch.full((1,), -7, dtype=torch.int32, device="cuda")
-        capi.ofm_ofmlmc_fit_indicators(ctx, 4, 1, mom, v_hat, flag, m_floor=m_floor)
+        capi.ofm_ofmlmc_fit_indicators(ctx, 4, 1, m_floor, mom, v_hat, flag)
         assert flag.item() == 0
         np.testing.assert_allclose(v_hat.cpu().numpy(), v_ref, rtol=1e-12, atol=0)
         m = mom.cpu().numpy()
