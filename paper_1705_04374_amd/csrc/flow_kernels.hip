@@ -584,7 +584,7 @@ stage_kernel(LaunchArgs a)
     // a workgroup's LDS is kept below 64 KiB: the one stage-kernel variant
     // above it (a running reduction held in LDS) computed states that
     // differed between tilings, for a cause not found (the set network's
-    // pooling kernel runs correctly with 73.7 KB); every variant that passed
+    // pooling kernel runs correctly with 73.2 KB); every variant that passed
     // the tiling-invariance test is below
     static_assert(sizeof(T) * (SPLIT ? WSZ + 2 * NV * ESX : AL + 2 * NV * ES) + sizeof(Red) * (NT / 64) <= 65536,
                   "stage kernel LDS above 64 KiB");

@@ -522,7 +522,7 @@ hipError_t nn_gemm_finish(const float* C, int splits, int64_t M, int N, int mode
 hipError_t nn_phi_pool(const float* x, const int32_t* offsets, int n_sets, const float* P, const uint16_t* W2bf,
                        float pool_scale, float* s_out, uint16_t* s_bf, uint16_t* h1_bf, float* z2, hipStream_t st)
 {
-    // two resident workgroups per CU (73.7 KB of LDS each): a few rounds of
+    // two resident workgroups per CU (73.2 KB of LDS each): a few rounds of
     // them, each taking sets gridDim.x apart
     const int grid = n_sets < 4096 ? n_sets : 4096;
     hipLaunchKernelGGL(phi_pool_kernel, dim3(grid), dim3(256), 0, st, x, offsets, n_sets, P, W2bf, pool_scale, s_out,
